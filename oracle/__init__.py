@@ -1,0 +1,192 @@
+"""CPU FP64 oracle for isoparametric P1/P2 finite-element assembly.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library ``paper_2605_14035_amd``; the two only read the
+same seeded meshes from ``meshgen``.
+
+The arithmetic lives in ``lfem_oracle.c`` (a plain element loop in the order
+of the paper's Listing 1) and ``quadrature.py`` (rules solved from their
+moment equations).  This module only marshals NumPy arrays through ctypes.
+
+Every function takes a mesh dict as produced by ``meshgen`` (keys
+``domain``, ``dim``, ``order``, ``quad``, ``coords`` (n_amb, N) float64,
+``conn`` (k, T) int32).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from . import quadrature
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lfem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, EDEGENERATE = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no vendor libraries)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        lp = C.POINTER(C.c_int64)
+        up = C.POINTER(C.c_uint8)
+        i64 = C.c_int64
+        ci = C.c_int
+        L.oracle_basis.argtypes = [ci, ci, dp, dp, dp]
+        L.oracle_element_matrices.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci,
+                                              i64, i64, dp]
+        L.oracle_assemble.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci, up, i64,
+                                      lp, ip, dp, lp]
+        L.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, C.c_double,
+                                    dp, dp, C.c_double, dp]
+        L.oracle_shape_grad.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp,
+                                        C.c_double, dp, dp, C.c_double, dp]
+        for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
+                  L.oracle_energy, L.oracle_shape_grad):
+            f.restype = ci
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _mesh_args(mesh, qp=None, qw=None):
+    surface = 1 if mesh["domain"] == "surface" else 0
+    d, p = int(mesh["dim"]), int(mesh["order"])
+    if qp is None:
+        qp, qw = quadrature.rule(d, int(mesh["quad"]))
+    qp = np.ascontiguousarray(qp, dtype=np.float64)
+    qw = np.ascontiguousarray(qw, dtype=np.float64)
+    coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
+    conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
+    N = coords.shape[1]
+    T = conn.shape[1]
+    keep = (qp, qw, coords, conn)
+    args = [surface, d, p, len(qw), _ptr(qp, C.c_double), _ptr(qw, C.c_double), N,
+            _ptr(coords, C.c_double), T, _ptr(conn, C.c_int32)]
+    return args, keep, N, T, conn.shape[0]
+
+
+def _check(st, what):
+    if st == EDEGENERATE:
+        raise FloatingPointError(f"{what}: degenerate element (measure not positive/finite)")
+    if st != OK:
+        raise RuntimeError(f"{what}: oracle status {st}")
+
+
+def basis(d: int, p: int, xi):
+    """Values (k,) and reference gradients (k, d) of the nodal basis at xi."""
+    xi = np.ascontiguousarray(np.atleast_1d(xi), dtype=np.float64)
+    k = (d + 1) if p == 1 else (d + 1) * (d + 2) // 2
+    phi = np.zeros(k)
+    dphi = np.zeros((k, d))
+    _check(lib().oracle_basis(d, p, _ptr(xi, C.c_double), _ptr(phi, C.c_double),
+                              _ptr(dphi, C.c_double)), "basis")
+    return phi, dphi
+
+
+KIND = {"mass": 0, "stiffness": 1}
+
+
+def element_matrices(mesh, kind: str, coef=None, e0: int = 0, e1=None, rule=None):
+    """Local k x k matrices of elements e0..e1-1 (mass or stiffness)."""
+    args, keep, N, T, k = _mesh_args(mesh, *(rule or (None, None)))
+    e1 = T if e1 is None else e1
+    coef = _f64(coef)
+    out = np.zeros((e1 - e0, k, k))
+    st = lib().oracle_element_matrices(*args, _ptr(coef, C.c_double), KIND[kind], e0, e1,
+                                       _ptr(out, C.c_double))
+    _check(st, "element_matrices")
+    return out
+
+
+def assemble(mesh, kind: str, coef=None, rows=None, rule=None):
+    """Global CSR (row_ptr int64 (N+1,), col_idx int32, vals float64).
+
+    ``rows``: optional iterable of row ids; only those rows are assembled
+    (all other rows come out empty)."""
+    args, keep, N, T, k = _mesh_args(mesh, *(rule or (None, None)))
+    conn = keep[3]
+    coef = _f64(coef)
+    mask = None
+    if rows is not None:
+        mask = np.zeros(N, dtype=np.uint8)
+        mask[np.asarray(rows, dtype=np.int64)] = 1
+        cap = int(mask[conn].sum()) * k
+    else:
+        cap = k * k * T
+    cap = max(cap, 1)
+    row_ptr = np.zeros(N + 1, dtype=np.int64)
+    col_idx = np.zeros(cap, dtype=np.int32)
+    vals = np.zeros(cap, dtype=np.float64)
+    nnz = np.zeros(1, dtype=np.int64)
+    st = lib().oracle_assemble(*args, _ptr(coef, C.c_double), KIND[kind],
+                               _ptr(mask, C.c_uint8), cap, _ptr(row_ptr, C.c_int64),
+                               _ptr(col_idx, C.c_int32), _ptr(vals, C.c_double),
+                               _ptr(nnz, C.c_int64))
+    _check(st, "assemble")
+    n = int(nnz[0])
+    return row_ptr, col_idx[:n].copy(), vals[:n].copy()
+
+
+def energy(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):
+    """alpha u^T A v + beta w^T M z."""
+    args, keep, N, T, k = _mesh_args(mesh)
+    u, v, w, z = _f64(u), _f64(v), _f64(w), _f64(z)
+    out = np.zeros(1)
+    st = lib().oracle_energy(*args, _ptr(u, C.c_double), _ptr(v, C.c_double), float(alpha),
+                             _ptr(w, C.c_double), _ptr(z, C.c_double), float(beta),
+                             _ptr(out, C.c_double))
+    _check(st, "energy")
+    return float(out[0])
+
+
+def shape_grad(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):
+    """d/dx [alpha u^T A(x) v + beta w^T M(x) z] as an (n_amb, N) array."""
+    args, keep, N, T, k = _mesh_args(mesh)
+    n_amb = keep[2].shape[0]
+    u, v, w, z = _f64(u), _f64(v), _f64(w), _f64(z)
+    g = np.zeros((n_amb, N))
+    st = lib().oracle_shape_grad(*args, _ptr(u, C.c_double), _ptr(v, C.c_double), float(alpha),
+                                 _ptr(w, C.c_double), _ptr(z, C.c_double), float(beta),
+                                 _ptr(g, C.c_double))
+    _check(st, "shape_grad")
+    return g
+
+
+def to_scipy(N, csr):
+    import scipy.sparse as sp
+    row_ptr, col_idx, vals = csr
+    return sp.csr_matrix((vals, col_idx, row_ptr), shape=(N, N))

@@ -1,0 +1,168 @@
+"""Oracle quadrature rules, solved from their moment equations.
+
+TEST INFRASTRUCTURE: only tests, the smoke check and the CPU-baseline leg of
+the benchmark use this package.  The GPU library never imports it.
+
+The paper integrates the local matrices with quadrature (section 3.2.2,
+equations for the quadrature mass and stiffness): a rule (xi_i, w_i) on the
+reference element with weights summing to the reference measure
+(1 segment, 1/2 triangle, 1/6 tetrahedron).  The rules used by the
+workloads are fixed here by *symmetry + moment equations*: the unknown orbit
+parameters are the roots of "the rule integrates every symmetric polynomial
+of degree <= p exactly", solved by Newton's method in 40-digit arithmetic and
+rounded to float64 at the end.
+
+Exact reference integrals used as right-hand sides (barycentric monomials):
+  triangle (area 1/2):  int l0^a l1^b l2^c = a! b! c! / (a+b+c+2)!
+  tetrahedron (vol 1/6): int l0^a l1^b l2^c l3^d = a! b! c! d! / (a+b+c+d+3)!
+"""
+
+from __future__ import annotations
+
+from functools import lru_cache
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+# rule id = (simplex dimension, number of points) -> polynomial degree
+DEGREE = {(1, 1): 1, (1, 2): 3, (1, 3): 5, (1, 4): 7, (1, 5): 9,
+          (2, 1): 1, (2, 3): 2, (2, 6): 4,
+          (3, 1): 1, (3, 4): 2, (3, 11): 4}
+
+
+def _bary_to_ref(lam):
+    """Barycentric (l0, ..., ld) -> reference coordinates (l1, ..., ld)."""
+    return [lam[i] for i in range(1, len(lam))]
+
+
+def _orbit(sym, params):
+    """All distinct permutations of a barycentric pattern."""
+    if sym == "S3":
+        return [[mp.mpf(1) / 3] * 3]
+    if sym == "S21":
+        a = params[0]
+        b = 1 - 2 * a
+        return [[a, a, b], [a, b, a], [b, a, a]]
+    if sym == "S4":
+        return [[mp.mpf(1) / 4] * 4]
+    if sym == "S31":
+        a = params[0]
+        b = 1 - 3 * a
+        return [[b, a, a, a], [a, b, a, a], [a, a, b, a], [a, a, a, b]]
+    if sym == "S22":
+        a = params[0]
+        b = mp.mpf(1) / 2 - a
+        pts = []
+        for i in range(4):
+            for j in range(i + 1, 4):
+                lam = [b] * 4
+                lam[i] = a
+                lam[j] = a
+                pts.append(lam)
+        return pts
+    raise ValueError(sym)
+
+
+def _sym_moments_tri(lam):
+    l0, l1, l2 = lam
+    return [mp.mpf(1), l0 ** 2 + l1 ** 2 + l2 ** 2, l0 * l1 * l2, l0 ** 4 + l1 ** 4 + l2 ** 4]
+
+
+_TRI_EXACT = [mp.mpf(1) / 2, mp.mpf(1) / 4, mp.mpf(1) / 120, mp.mpf(1) / 10]
+
+
+def _sym_moments_tet(lam):
+    s2 = sum(x ** 2 for x in lam)
+    s3 = sum(x ** 3 for x in lam)
+    s4 = sum(x ** 4 for x in lam)
+    s22 = sum(lam[i] ** 2 * lam[j] ** 2 for i in range(4) for j in range(i + 1, 4))
+    return [mp.mpf(1), s2, s3, s4, s22]
+
+
+_TET_EXACT = [mp.mpf(1) / 6, mp.mpf(1) / 15, mp.mpf(1) / 30, mp.mpf(2) / 105, mp.mpf(1) / 210]
+
+
+def _solve(orbits, moments, exact, x0):
+    """orbits: list of (sym, n_params); unknowns per orbit: weight, params."""
+    def residual(*x):
+        x = list(x)
+        total = [mp.mpf(0)] * len(exact)
+        for sym, npar in orbits:
+            w = x.pop(0)
+            params = [x.pop(0) for _ in range(npar)]
+            for lam in _orbit(sym, params):
+                m = moments(lam)
+                for i in range(len(exact)):
+                    total[i] += w * m[i]
+        return [total[i] - exact[i] for i in range(len(exact))]
+    sol = mp.findroot(residual, [mp.mpf(v) for v in x0], tol=mp.mpf(10) ** -36)
+    sol = [sol[i] for i in range(len(x0))] if hasattr(sol, "__len__") else [sol]
+    pts, wts = [], []
+    sol = list(sol)
+    for sym, npar in orbits:
+        w = sol.pop(0)
+        params = [sol.pop(0) for _ in range(npar)]
+        for lam in _orbit(sym, params):
+            pts.append(_bary_to_ref(lam))
+            wts.append(w)
+    return pts, wts
+
+
+def _gauss_legendre(n):
+    """n-point Gauss-Legendre on [0, 1]: roots of P_n by Newton."""
+    pts, wts = [], []
+    for i in range(1, n + 1):
+        x0 = mp.cos(mp.pi * (i - mp.mpf(1) / 4) / (n + mp.mpf(1) / 2))
+        x = mp.findroot(lambda t: mp.legendre(n, t), x0)
+        dp = mp.diff(lambda t: mp.legendre(n, t), x)
+        w = 2 / ((1 - x ** 2) * dp ** 2)
+        pts.append([(1 + x) / 2])
+        wts.append(w / 2)
+    order = sorted(range(n), key=lambda i: pts[i][0])
+    return [pts[i] for i in order], [wts[i] for i in order]
+
+
+@lru_cache(maxsize=None)
+def _rule_mp(dim: int, npts: int):
+    if dim == 1:
+        return _gauss_legendre(npts)
+    if dim == 2:
+        if npts == 1:
+            return _solve([("S3", 0)], lambda l: [mp.mpf(1)], [mp.mpf(1) / 2], [0.5])
+        if npts == 3:
+            # interior orbit (a, a, 1-2a) with a near 1/6 (the other root, a = 1/2,
+            # is the edge-midpoint rule)
+            return _solve([("S21", 1)], lambda l: _sym_moments_tri(l)[:2], _TRI_EXACT[:2],
+                          [0.16, 0.15])
+        if npts == 6:
+            return _solve([("S21", 1), ("S21", 1)], _sym_moments_tri, _TRI_EXACT,
+                          [0.11, 0.44, 0.05, 0.09])
+    if dim == 3:
+        if npts == 1:
+            return _solve([("S4", 0)], lambda l: [mp.mpf(1)], [mp.mpf(1) / 6], [0.1])
+        if npts == 4:
+            return _solve([("S31", 1)], lambda l: _sym_moments_tet(l)[:2], _TET_EXACT[:2],
+                          [0.04, 0.14])
+        if npts == 11:
+            return _solve([("S4", 0), ("S31", 1), ("S22", 1)], _sym_moments_tet, _TET_EXACT,
+                          [-0.013, 0.0076, 0.07, 0.025, 0.4])
+    raise ValueError(f"no rule with {npts} points on the {dim}-simplex")
+
+
+def rule(dim: int, npts: int):
+    """(points (Q, dim) float64 in reference coordinates, weights (Q,) float64)."""
+    pts, wts = _rule_mp(dim, npts)
+    P = np.array([[float(c) for c in p] for p in pts], dtype=np.float64).reshape(npts, dim)
+    W = np.array([float(w) for w in wts], dtype=np.float64)
+    return P, W
+
+
+def rule_mp(dim: int, npts: int):
+    """The same rule in 40-digit arithmetic (for the exactness pins)."""
+    return _rule_mp(dim, npts)
+
+
+def degree(dim: int, npts: int) -> int:
+    return DEGREE[(dim, npts)]
