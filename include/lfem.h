@@ -1,0 +1,211 @@
+/*
+ * lfem.h -- C ABI of the MI355X (gfx950) isoparametric finite-element
+ * assembly library (liblfem.so).
+ *
+ * What it computes.  For a mesh of linear (P1) or quadratic (P2)
+ * isoparametric simplices -- curves in R^2, surfaces in R^3, bulk domains in
+ * R^2 and R^3 (the element types of the paper's table of supported elements,
+ * section 5) -- it assembles in FP64:
+ *
+ *   mass              M_ij   = sum_E sum_q w_q mu_E(xi_q) phi_i phi_j
+ *   stiffness         A_ij   = sum_E sum_q w_q mu_E(xi_q) grad phi_i . grad phi_j
+ *   weighted mass     Mc_ij  = sum_E sum_q w_q mu_E(xi_q) c_h(xi_q) phi_i phi_j
+ *   coefficient stiffness: A with the factor a_h(xi_q) inside the sum
+ *
+ * (section 3.2: elementwise splitting of M and A, the local mass and
+ * stiffness matrices, and their quadrature forms).  grad is the tangential
+ * gradient on curves and surfaces (section 2.1, discrete tangential
+ * gradient) and the ordinary gradient in bulk; mu is the surface/curve
+ * measure |t1 x t2| or |t|, or |det DF| in bulk (section 3.2.1 and
+ * Listing 1 (c)).  Nodal coefficients are interpolated with the element
+ * basis: c_h = sum_r c_r phi_r.  Results are summed into a CSR matrix whose
+ * pattern is structural: every (i, j) that share an element, diagonal
+ * included, columns ascending, no entry dropped for being zero.
+ *
+ * Conventions for every entry point.
+ *  - Indices are 0-based int32.  Coordinates are structure-of-arrays:
+ *    coords[c * N + i] is coordinate c of node i (the paper's node array N,
+ *    section 4).  Connectivity is structure-of-arrays: conn[a * T + e] is
+ *    local node a of element e (the paper's element array E), corners first
+ *    in anticlockwise order, then edge nodes: segment (0,1); triangle
+ *    (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2), (0,2), (0,3), (1,3), (2,3).
+ *  - Every array argument is a DEVICE pointer owned by the caller; the
+ *    library never frees it.  A mesh keeps the coords / conn pointers it was
+ *    given (no copy): they must stay valid, and conn unchanged, for the
+ *    mesh's lifetime.  Handles own their internal device buffers and release
+ *    them in the matching *_destroy call.
+ *  - stream is a hipStream_t passed as void* (NULL: the default stream).
+ *    Calls enqueue work and return without waiting, except where a call says
+ *    that it synchronises.
+ *  - Every call returns an lfem_status; no exception crosses the ABI.  On an
+ *    error lfem_last_error() returns a thread-local message.
+ *  - Calls that share a handle must not overlap on different streams.
+ */
+#ifndef LFEM_H
+#define LFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lfem_status;
+#define LFEM_OK 0
+#define LFEM_EINVAL 1          /* bad argument (null pointer, bad size, index out of range) */
+#define LFEM_ENOMEM 2          /* device or host allocation failed */
+#define LFEM_EHIP 3            /* a HIP runtime call failed */
+#define LFEM_ERANGE 4          /* nnz or an index would not fit in int32 */
+#define LFEM_EDEGENERATE 5     /* degenerate elements were found */
+#define LFEM_EUNSUPPORTED 6    /* element type / rule / option not supported */
+
+/* domains */
+#define LFEM_SURFACE 0         /* d-manifold in R^(d+1): curve (d=1) or surface (d=2) */
+#define LFEM_BULK 1            /* d-dimensional domain in R^d, d = 2 or 3 */
+
+/* matrix selection bits */
+#define LFEM_M 1u              /* mass */
+#define LFEM_A 2u              /* stiffness (optionally with a nodal coefficient) */
+#define LFEM_MC 4u             /* weighted mass with a nodal coefficient */
+
+/* numeric scatter variants (how local matrices are summed into CSR values) */
+#define LFEM_SCATTER_AUTO 0     /* the pattern's tuned choice (blocked unless tuned otherwise) */
+#define LFEM_SCATTER_BLOCKED 1  /* deterministic: row blocks accumulated in LDS, colour order */
+#define LFEM_SCATTER_STAGED 2   /* deterministic: local matrices staged, slot-sorted segmented sum */
+#define LFEM_SCATTER_ATOMIC 3   /* FP64 atomics into zeroed values; summation order not fixed */
+
+typedef struct lfem_mesh_s *lfem_mesh_t;
+typedef struct lfem_pattern_s *lfem_pattern_t;
+typedef struct lfem_batch_s *lfem_batch_t;
+
+/*
+ * Create a mesh handle.  domain: LFEM_SURFACE or LFEM_BULK; dim: manifold
+ * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1 or 2.  The ambient
+ * dimension is n_amb = d + 1 (surface) or d (bulk), so coords has
+ * n_amb * n_nodes entries and conn has k * n_elems entries, k = C(order+d, d).
+ * quad_points selects the quadrature rule on the reference simplex by its
+ * number of points (0: the default for the element type):
+ *   segment: 2 (Gauss, degree 3, P1 default), 3 (Gauss, degree 5, P2 default)
+ *   triangle: 3 (interior orbit, degree 2, P1 default), 6 (degree 4, P2 default)
+ *   tetrahedron: 4 (degree 2, P1 default), 11 (degree 4, P2 default)
+ * The rules are those of the paper's quadrature forms (section 3.2.2) with the
+ * weights summing to the reference measure.  Builds the node -> element
+ * incidence on the device (asynchronous on stream).
+ * Errors: LFEM_EINVAL (sizes, nulls, n_elems * k >= 2^31),
+ * LFEM_EUNSUPPORTED (type/rule), LFEM_ENOMEM, LFEM_EHIP.
+ */
+lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
+                             const double *coords, int64_t n_elems, const int32_t *conn,
+                             int quad_points, void *stream, lfem_mesh_t *out);
+
+/* Point the mesh at new coordinates (moving mesh, same topology).  The next
+ * assembly reads them; nothing is recomputed eagerly. */
+lfem_status lfem_mesh_set_coords(lfem_mesh_t m, const double *coords);
+
+/*
+ * Symbolic phase (once per topology): build the CSR pattern, the
+ * element -> CSR slot map (one byte per local pair: the column offset inside
+ * the row) and the row-block schedule of the blocked scatter.  The pattern is
+ * the structural sparsity of the element array (the paper's sparse() step
+ * without its value-dependent dropping).  SYNCHRONISES stream once to learn
+ * nnz and to build the block schedule on the host.
+ * Errors: LFEM_EINVAL (a conn entry outside [0, N) or repeated inside an
+ * element), LFEM_ERANGE (nnz >= 2^31, or a row with more than 255 entries),
+ * LFEM_ENOMEM, LFEM_EHIP.
+ */
+lfem_status lfem_pattern_build(lfem_mesh_t m, void *stream, lfem_pattern_t *out);
+
+/* Pattern sizes and device pointers (owned by the pattern): row_ptr has
+ * n_rows + 1 entries, col_idx has nnz entries.  Any output may be NULL. */
+lfem_status lfem_pattern_get(lfem_pattern_t p, int64_t *n_rows, int64_t *nnz,
+                             const int32_t **row_ptr, const int32_t **col_idx);
+
+/*
+ * Numeric phase, any subset of matrices in one pass over the elements.
+ * what: bitwise OR of LFEM_M, LFEM_A, LFEM_MC.  coef_a: nodal coefficient
+ * [N] inside the stiffness (NULL: 1).  coef_c: nodal coefficient [N] of the
+ * weighted mass (required with LFEM_MC).  vals_m / vals_a / vals_mc: outputs
+ * of nnz doubles each, overwritten (required for the selected matrices).
+ * scatter: LFEM_SCATTER_*.  The blocked and staged scatters are bitwise
+ * reproducible run to run; the atomic one is not.
+ * Degenerate elements (measure not positive and finite) still produce values
+ * and increment the mesh's counter (lfem_status_get).
+ */
+lfem_status lfem_assemble(lfem_mesh_t m, lfem_pattern_t p, unsigned what, const double *coef_a,
+                          const double *coef_c, double *vals_m, double *vals_a, double *vals_mc,
+                          int scatter, void *stream);
+
+/* Single-matrix shorthands of lfem_assemble with LFEM_SCATTER_AUTO. */
+lfem_status lfem_assemble_mass(lfem_mesh_t m, lfem_pattern_t p, double *vals, void *stream);
+lfem_status lfem_assemble_stiffness(lfem_mesh_t m, lfem_pattern_t p, const double *coef,
+                                    double *vals, void *stream);
+lfem_status lfem_assemble_weighted(lfem_mesh_t m, lfem_pattern_t p, const double *coef,
+                                   double *vals, void *stream);
+
+/*
+ * Autotune the scatter variant and row-block size of pattern p for the
+ * matrix set `what` by timing the candidates on stream (SYNCHRONISES).
+ * The choice is kept in the pattern and used by LFEM_SCATTER_AUTO.
+ * *variant_out (may be NULL) receives the chosen LFEM_SCATTER_* value.
+ * Scratch outputs are allocated and freed inside.
+ */
+lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what, void *stream,
+                                  int *variant_out);
+
+/*
+ * Batched assembly: many meshes (any element types, uneven sizes) assembled
+ * in one persistent launch replayed from a HIP graph.  what: matrices per
+ * mesh (LFEM_M | LFEM_A; coefficients are not supported in batches).
+ * autotune != 0 times the candidate launch shapes once at creation
+ * (SYNCHRONISES stream).  The handle keeps the mesh and pattern handles
+ * (which must outlive it).
+ */
+lfem_status lfem_batch_create(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
+                              unsigned what, int autotune, void *stream, lfem_batch_t *out);
+
+/*
+ * Run the batch.  vals[i * nmat + j] is the output of matrix j of mesh i,
+ * nmat = number of bits in `what`, ordered M then A; each has that mesh's
+ * nnz doubles and is overwritten.  When the pointer set differs from the
+ * previous call the library waits for the previous call to finish before
+ * updating its device-side pointer table.
+ */
+lfem_status lfem_assemble_batch(lfem_batch_t b, double *const *vals, void *stream);
+
+/*
+ * Shape derivative (adjoint) of
+ *     J(x) = alpha u^T A(x) v + beta w^T M(x) z
+ * with respect to every node coordinate: grad[c * N + r] = dJ / dx_{r,c}
+ * (n_amb * N doubles, overwritten).  u, v, w, z: nodal vectors [N]; the A
+ * term is skipped when u or v is NULL, the M term when w or z is NULL.
+ * Deterministic (fixed summation order).  Plain A and M only (no coefficients).
+ */
+lfem_status lfem_shape_grad(lfem_mesh_t m, const double *u, const double *v, double alpha,
+                            const double *w, const double *z, double beta, double *grad,
+                            void *stream);
+
+/* Matrix-free value of the same J(x) into the device scalar *J_out. */
+lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double alpha,
+                        const double *w, const double *z, double beta, double *J_out,
+                        void *stream);
+
+/* Number of degenerate (element, quadrature point) evaluations seen by this
+ * mesh since creation or the last reset.  SYNCHRONISES the device. */
+lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate);
+lfem_status lfem_status_reset(lfem_mesh_t m, void *stream);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *lfem_last_error(void);
+
+/* Library version string. */
+const char *lfem_version(void);
+
+void lfem_mesh_destroy(lfem_mesh_t m);
+void lfem_pattern_destroy(lfem_pattern_t p);
+void lfem_batch_destroy(lfem_batch_t b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFEM_H */

@@ -27,29 +27,34 @@ from . import quadrature
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lfem_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source in 80-bit long double: finite-difference reference only
+_LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
 
 OK, EINVAL, ENOMEM, EDEGENERATE = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no vendor libraries)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
-                       check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain -O2, no vendor libraries), plus the
+    long-double build used as a finite-difference reference."""
+    for path, extra in ((_LIB, []), (_LIB_LD, ["-DORACLE_LONG_DOUBLE"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp,
+                            _SRC, "-lm"], check=True)
+            os.replace(tmp, path)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+def lib(long_double: bool = False):
+    key = bool(long_double)
+    if key not in _libs:
+        path = _LIB_LD if key else _LIB
+        if not os.path.exists(path):
+            build(force=False)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         lp = C.POINTER(C.c_int64)
@@ -68,8 +73,8 @@ def lib():
         for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
                   L.oracle_energy, L.oracle_shape_grad):
             f.restype = ci
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _ptr(a, ctype):
@@ -161,12 +166,13 @@ def assemble(mesh, kind: str, coef=None, rows=None, rule=None):
     return row_ptr, col_idx[:n].copy(), vals[:n].copy()
 
 
-def energy(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):
-    """alpha u^T A v + beta w^T M z."""
+def energy(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0, long_double=False):
+    """alpha u^T A v + beta w^T M z.  ``long_double`` evaluates it with the
+    80-bit build (finite-difference reference)."""
     args, keep, N, T, k = _mesh_args(mesh)
     u, v, w, z = _f64(u), _f64(v), _f64(w), _f64(z)
     out = np.zeros(1)
-    st = lib().oracle_energy(*args, _ptr(u, C.c_double), _ptr(v, C.c_double), float(alpha),
+    st = lib(long_double).oracle_energy(*args, _ptr(u, C.c_double), _ptr(v, C.c_double), float(alpha),
                              _ptr(w, C.c_double), _ptr(z, C.c_double), float(beta),
                              _ptr(out, C.c_double))
     _check(st, "energy")

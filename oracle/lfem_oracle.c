@@ -37,6 +37,20 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Internal arithmetic type.  The oracle is built with double.  The same
+ * source built with -DORACLE_LONG_DOUBLE serves only as a finite-difference
+ * reference for the shape-derivative pins: its energy rounds ~2^11 times
+ * less, so a central difference with h = 1e-6 is not dominated by round-off. */
+#ifdef ORACLE_LONG_DOUBLE
+typedef long double real;
+#define r_sqrt sqrtl
+#define r_fabs fabsl
+#else
+typedef double real;
+#define r_sqrt sqrt
+#define r_fabs fabs
+#endif
+
 #define OR_OK 0
 #define OR_EINVAL 1
 #define OR_ENOMEM 2
@@ -60,9 +74,9 @@ int oracle_nodes_per_element(int d, int p)
 }
 
 /* phi[a], dphi[a*d + m] = d phi_a / d xi_m at reference point xi[0..d-1] */
-int oracle_basis(int d, int p, const double *xi, double *phi, double *dphi)
+static int basis_r(int d, int p, const real *xi, real *phi, real *dphi)
 {
-    double lam[DMAX + 1], dlam[DMAX + 1][DMAX];
+    real lam[DMAX + 1], dlam[DMAX + 1][DMAX];
     int i, m;
     if (d < 1 || d > 3 || p < 1 || p > 2) return OR_EINVAL;
     lam[0] = 1.0;
@@ -100,13 +114,25 @@ int oracle_basis(int d, int p, const double *xi, double *phi, double *dphi)
     return OR_OK;
 }
 
+int oracle_basis(int d, int p, const double *xi, double *phi, double *dphi)
+{
+    real x[DMAX], f[KMAX], g[KMAX * DMAX];
+    int i, st;
+    if (d < 1 || d > 3 || p < 1 || p > 2) return OR_EINVAL;
+    for (i = 0; i < d; i++) x[i] = xi[i];
+    st = basis_r(d, p, x, f, g);
+    for (i = 0; i < oracle_nodes_per_element(d, p); i++) phi[i] = (double)f[i];
+    for (i = 0; i < oracle_nodes_per_element(d, p) * d; i++) dphi[i] = (double)g[i];
+    return st;
+}
+
 /* ---------------------------------------------------------------------- */
 /* small dense linear algebra                                              */
 /* ---------------------------------------------------------------------- */
 /* inverse of an n x n matrix (n = 1, 2, 3) stored row-major; returns det */
-static double inverse_small(int n, const double *L, double *C)
+static real inverse_small(int n, const real *L, real *C)
 {
-    double det;
+    real det;
     if (n == 1) {
         det = L[0];
         C[0] = 1.0 / det;
@@ -122,15 +148,15 @@ static double inverse_small(int n, const double *L, double *C)
     }
     /* 3 x 3: C = adj(L) / det(L), adj = transpose of the cofactor matrix */
     {
-        double c00 = L[4] * L[8] - L[5] * L[7];
-        double c01 = -(L[3] * L[8] - L[5] * L[6]);
-        double c02 = L[3] * L[7] - L[4] * L[6];
-        double c10 = -(L[1] * L[8] - L[2] * L[7]);
-        double c11 = L[0] * L[8] - L[2] * L[6];
-        double c12 = -(L[0] * L[7] - L[1] * L[6]);
-        double c20 = L[1] * L[5] - L[2] * L[4];
-        double c21 = -(L[0] * L[5] - L[2] * L[3]);
-        double c22 = L[0] * L[4] - L[1] * L[3];
+        real c00 = L[4] * L[8] - L[5] * L[7];
+        real c01 = -(L[3] * L[8] - L[5] * L[6]);
+        real c02 = L[3] * L[7] - L[4] * L[6];
+        real c10 = -(L[1] * L[8] - L[2] * L[7]);
+        real c11 = L[0] * L[8] - L[2] * L[6];
+        real c12 = -(L[0] * L[7] - L[1] * L[6]);
+        real c20 = L[1] * L[5] - L[2] * L[4];
+        real c21 = -(L[0] * L[5] - L[2] * L[3]);
+        real c22 = L[0] * L[4] - L[1] * L[3];
         det = L[0] * c00 + L[1] * c01 + L[2] * c02;
         C[0] = c00 / det; C[1] = c10 / det; C[2] = c20 / det;
         C[3] = c01 / det; C[4] = c11 / det; C[5] = c21 / det;
@@ -153,17 +179,21 @@ typedef struct {
 /* For element e at quadrature point q: phi[k], grad[k][n] (physical / tangential
    gradients) and mu.  Returns 0, or OR_EDEGENERATE when mu is not positive
    and finite. */
-static int point_geometry(const etype *t, const double *x /*[k][n]*/, int q, double *phi,
-                          double *grad, double *mu_out)
+static int point_geometry(const etype *t, const real *x /*[k][n]*/, int q, real *phi,
+                          real *grad, real *mu_out)
 {
-    double dphi[KMAX * DMAX];
-    double L[9], C[9], tm[DMAX][DMAX]; /* tm[m][c] = tangent m, component c */
+    real dphi[KMAX * DMAX];
+    real L[9], C[9], tm[DMAX][DMAX]; /* tm[m][c] = tangent m, component c */
     int a, c, m, r, s, n = t->n, d = t->d;
-    double mu;
-    oracle_basis(d, t->p, t->qp + q * d, phi, dphi);
+    real mu;
+    {
+        real xi[DMAX];
+        for (m = 0; m < d; m++) xi[m] = t->qp[q * d + m];
+        basis_r(d, t->p, xi, phi, dphi);
+    }
     for (m = 0; m < d; m++)
         for (c = 0; c < n; c++) {
-            double acc = 0.0;
+            real acc = 0.0;
             for (a = 0; a < t->k; a++) acc += x[a * n + c] * dphi[a * d + m];
             tm[m][c] = acc;
         }
@@ -172,26 +202,26 @@ static int point_geometry(const etype *t, const double *x /*[k][n]*/, int q, dou
         for (m = 0; m < d; m++) L[c * n + m] = tm[m][c];
     if (t->surface) {
         if (d == 2) { /* third column t1 x t2 */
-            double nx = tm[0][1] * tm[1][2] - tm[0][2] * tm[1][1];
-            double ny = tm[0][2] * tm[1][0] - tm[0][0] * tm[1][2];
-            double nz = tm[0][0] * tm[1][1] - tm[0][1] * tm[1][0];
+            real nx = tm[0][1] * tm[1][2] - tm[0][2] * tm[1][1];
+            real ny = tm[0][2] * tm[1][0] - tm[0][0] * tm[1][2];
+            real nz = tm[0][0] * tm[1][1] - tm[0][1] * tm[1][0];
             L[0 * 3 + 2] = nx;
             L[1 * 3 + 2] = ny;
             L[2 * 3 + 2] = nz;
-            mu = sqrt(nx * nx + ny * ny + nz * nz);
+            mu = r_sqrt(nx * nx + ny * ny + nz * nz);
         } else { /* curve in R^2: second column t_perp */
             L[0 * 2 + 1] = -tm[0][1];
             L[1 * 2 + 1] = tm[0][0];
-            mu = sqrt(tm[0][0] * tm[0][0] + tm[0][1] * tm[0][1]);
+            mu = r_sqrt(tm[0][0] * tm[0][0] + tm[0][1] * tm[0][1]);
         }
         inverse_small(n, L, C);
     } else {
-        mu = fabs(inverse_small(n, L, C));
+        mu = r_fabs(inverse_small(n, L, C));
     }
     /* grad phi_a = C^T [g_a ; 0]: component r = sum_s C[s][r] g_ext[s] */
     for (a = 0; a < t->k; a++)
         for (r = 0; r < n; r++) {
-            double acc = 0.0;
+            real acc = 0.0;
             for (s = 0; s < d; s++) acc += C[s * n + r] * dphi[a * d + s];
             grad[a * n + r] = acc;
         }
@@ -217,7 +247,7 @@ static int make_type(etype *t, int surface, int d, int p, int Q, const double *q
 }
 
 static void gather(const etype *t, int64_t N, const double *coords, int64_t T,
-                   const int32_t *conn, int64_t e, double *x)
+                   const int32_t *conn, int64_t e, real *x)
 {
     int a, c;
     for (a = 0; a < t->k; a++) {
@@ -230,16 +260,16 @@ static void gather(const etype *t, int64_t N, const double *coords, int64_t T,
    basis (c_h = sum_r c_r phi_r), or NULL for 1.  out: k*k row-major. */
 static int element_matrix(const etype *t, int64_t N, const double *coords, int64_t T,
                           const int32_t *conn, const double *coef, int kind, int64_t e,
-                          double *out)
+                          real *out)
 {
-    double x[KMAX * DMAX], phi[KMAX], grad[KMAX * DMAX], ce[KMAX];
+    real x[KMAX * DMAX], phi[KMAX], grad[KMAX * DMAX], ce[KMAX];
     int q, a, b, r, k = t->k, n = t->n, status = OR_OK;
     gather(t, N, coords, T, conn, e, x);
     if (coef)
         for (a = 0; a < k; a++) ce[a] = coef[conn[(int64_t)a * T + e]];
-    memset(out, 0, sizeof(double) * k * k);
+    for (a = 0; a < k * k; a++) out[a] = 0;
     for (q = 0; q < t->Q; q++) {
-        double mu, f = 1.0, wmu;
+        real mu, f = 1.0, wmu;
         if (point_geometry(t, x, q, phi, grad, &mu)) status = OR_EDEGENERATE;
         if (coef) {
             f = 0.0;
@@ -248,7 +278,7 @@ static int element_matrix(const etype *t, int64_t N, const double *coords, int64
         wmu = t->qw[q] * mu * f;
         for (a = 0; a < k; a++)
             for (b = 0; b < k; b++) {
-                double v;
+                real v;
                 if (kind == 0) {
                     v = phi[a] * phi[b];
                 } else {
@@ -270,10 +300,12 @@ int oracle_element_matrices(int surface, int d, int p, int Q, const double *qp,
     int64_t e;
     int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
     if (st) return st;
-    for (e = e0; e < e1; e++)
-        if (element_matrix(&t, N, coords, T, conn, coef, kind, e,
-                           out + (e - e0) * t.k * t.k))
-            bad = 1;
+    for (e = e0; e < e1; e++) {
+        real loc[KMAX * KMAX];
+        int i;
+        if (element_matrix(&t, N, coords, T, conn, coef, kind, e, loc)) bad = 1;
+        for (i = 0; i < t.k * t.k; i++) out[(e - e0) * t.k * t.k + i] = (double)loc[i];
+    }
     return bad ? OR_EDEGENERATE : OR_OK;
 }
 
@@ -283,7 +315,7 @@ int oracle_element_matrices(int surface, int d, int p, int Q, const double *qp,
 /* Two stable counting sorts (by column, then by row) give the (row, col)
    lexicographic order while keeping element order among equal keys. */
 static int coo_to_csr(int64_t N, int64_t m, const int32_t *I, const int32_t *J,
-                      const double *V, int64_t *row_ptr, int32_t *col_idx, double *vals,
+                      const real *V, int64_t *row_ptr, int32_t *col_idx, double *vals,
                       int64_t *nnz_out)
 {
     int64_t *cnt = calloc((size_t)N + 1, sizeof(int64_t));
@@ -308,13 +340,13 @@ static int coo_to_csr(int64_t N, int64_t m, const int32_t *I, const int32_t *J,
     for (i = 0; i <= N; i++) row_ptr[i] = 0;
     for (s = 0; s < m;) {
         int64_t src = p2[s], t = s + 1;
-        double acc = V[src];
+        real acc = V[src];
         while (t < m && I[p2[t]] == I[src] && J[p2[t]] == J[src]) {
             acc += V[p2[t]];
             t++;
         }
         col_idx[nnz] = J[src];
-        vals[nnz] = acc;
+        vals[nnz] = (double)acc;
         row_ptr[I[src] + 1]++;
         nnz++;
         s = t;
@@ -343,7 +375,7 @@ int oracle_assemble(int surface, int d, int p, int Q, const double *qp, const do
     int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
     int64_t e, m = 0, k2;
     int32_t *I, *J;
-    double *V, loc[KMAX * KMAX];
+    real *V, loc[KMAX * KMAX];
     if (st) return st;
     k2 = (int64_t)t.k * t.k;
     /* count the triples to keep */
@@ -357,7 +389,7 @@ int oracle_assemble(int surface, int d, int p, int Q, const double *qp, const do
     }
     I = malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
     J = malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
-    V = malloc(sizeof(double) * (size_t)(m ? m : 1));
+    V = malloc(sizeof(real) * (size_t)(m ? m : 1));
     if (!I || !J || !V) {
         free(I); free(J); free(V);
         return OR_ENOMEM;
@@ -405,11 +437,11 @@ int oracle_energy(int surface, int d, int p, int Q, const double *qp, const doub
     etype t;
     int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
     int64_t e;
-    double loc[KMAX * KMAX], J = 0.0;
+    real loc[KMAX * KMAX], J = 0.0;
     if (st) return st;
     for (e = 0; e < T; e++) {
         int a, b;
-        double ea = 0.0, em = 0.0;
+        real ea = 0.0, em = 0.0;
         if (u && v && alpha != 0.0) {
             if (element_matrix(&t, N, coords, T, conn, NULL, 1, e, loc)) bad = 1;
             for (a = 0; a < t.k; a++)
@@ -426,7 +458,7 @@ int oracle_energy(int surface, int d, int p, int Q, const double *qp, const doub
         }
         J += alpha * ea + beta * em;
     }
-    *J_out = J;
+    *J_out = (double)J;
     return bad ? OR_EDEGENERATE : OR_OK;
 }
 
@@ -452,8 +484,8 @@ int oracle_shape_grad(int surface, int d, int p, int Q, const double *qp, const 
     if (st) return st;
     memset(grad, 0, sizeof(double) * (size_t)(t.n * N));
     for (e = 0; e < T; e++) {
-        double x[KMAX * DMAX], phi[KMAX], gp[KMAX * DMAX];
-        double ue[KMAX], ve[KMAX], we[KMAX], ze[KMAX];
+        real x[KMAX * DMAX], phi[KMAX], gp[KMAX * DMAX];
+        real ue[KMAX], ve[KMAX], we[KMAX], ze[KMAX];
         int a, q, c, k = t.k, n = t.n;
         gather(&t, N, coords, T, conn, e, x);
         for (a = 0; a < k; a++) {
@@ -464,7 +496,7 @@ int oracle_shape_grad(int surface, int d, int p, int Q, const double *qp, const 
             ze[a] = z ? z[g] : 0.0;
         }
         for (q = 0; q < t.Q; q++) {
-            double mu, gu[DMAX] = {0}, gv[DMAX] = {0}, wh = 0.0, zh = 0.0, uv = 0.0;
+            real mu, gu[DMAX] = {0}, gv[DMAX] = {0}, wh = 0.0, zh = 0.0, uv = 0.0;
             if (point_geometry(&t, x, q, phi, gp, &mu)) bad = 1;
             for (a = 0; a < k; a++) {
                 for (c = 0; c < n; c++) {
@@ -476,16 +508,16 @@ int oracle_shape_grad(int surface, int d, int p, int Q, const double *qp, const 
             }
             for (c = 0; c < n; c++) uv += gu[c] * gv[c];
             for (a = 0; a < k; a++) {
-                double pu = 0.0, pv = 0.0;
+                real pu = 0.0, pv = 0.0;
                 int64_t g = conn[(int64_t)a * T + e];
                 for (c = 0; c < n; c++) {
                     pu += gp[a * n + c] * gu[c];
                     pv += gp[a * n + c] * gv[c];
                 }
                 for (c = 0; c < n; c++) {
-                    double dA = uv * gp[a * n + c] - pu * gv[c] - pv * gu[c];
-                    double dM = wh * zh * gp[a * n + c];
-                    grad[(int64_t)c * N + g] += t.qw[q] * mu * (alpha * dA + beta * dM);
+                    real dA = uv * gp[a * n + c] - pu * gv[c] - pv * gu[c];
+                    real dM = wh * zh * gp[a * n + c];
+                    grad[(int64_t)c * N + g] += (double)(t.qw[q] * mu * (alpha * dA + beta * dM));
                 }
             }
         }

@@ -1,0 +1,210 @@
+"""MI355X-native isoparametric finite-element assembly (liblfem.so binding).
+
+The functions below carry the names of the C ABI in ``include/lfem.h`` and
+only marshal arguments: PyTorch tensors (device memory, FP64 / int32,
+contiguous) are passed as raw device pointers, the current PyTorch stream as
+the HIP stream, and a non-OK status becomes ``LfemError``.  Every step of the
+computation runs in the library's HIP kernels; importing this package
+without a built ``liblfem.so`` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_ATOMIC, LFEM_SCATTER_AUTO,
+                   LFEM_SCATTER_BLOCKED, LFEM_SCATTER_STAGED, LFEM_SURFACE, LfemError)
+
+_L = _lib.load()
+
+__all__ = [
+    "LFEM_A", "LFEM_BULK", "LFEM_M", "LFEM_MC", "LFEM_SCATTER_ATOMIC", "LFEM_SCATTER_AUTO",
+    "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LfemError",
+    "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
+    "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
+    "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
+    "lfem_energy", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
+    "library_path",
+]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live in device memory")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def lfem_mesh_create(domain: int, dim: int, order: int, coords: torch.Tensor, conn: torch.Tensor,
+                     quad_points: int = 0, stream=None) -> C.c_void_p:
+    """coords: float64 (n_amb, N); conn: int32 (k, T).  Both must outlive the mesh."""
+    out = C.c_void_p()
+    N = coords.shape[1] if coords.dim() == 2 else 0
+    T = conn.shape[1] if conn.dim() == 2 else 0
+    st = _L.lfem_mesh_create(int(domain), int(dim), int(order), N,
+                             _ptr(coords, torch.float64, "coords"), T,
+                             _ptr(conn, torch.int32, "conn"), int(quad_points), _stream(stream),
+                             C.byref(out))
+    _lib.check(st, "lfem_mesh_create")
+    return out
+
+
+def lfem_mesh_set_coords(mesh, coords: torch.Tensor):
+    _lib.check(_L.lfem_mesh_set_coords(mesh, _ptr(coords, torch.float64, "coords")),
+               "lfem_mesh_set_coords")
+
+
+def lfem_pattern_build(mesh, stream=None) -> C.c_void_p:
+    out = C.c_void_p()
+    _lib.check(_L.lfem_pattern_build(mesh, _stream(stream), C.byref(out)), "lfem_pattern_build")
+    return out
+
+
+def lfem_pattern_get(pattern):
+    """(n_rows, nnz, row_ptr device address, col_idx device address)."""
+    n, nnz = C.c_int64(), C.c_int64()
+    rp, ci = C.c_void_p(), C.c_void_p()
+    _lib.check(_L.lfem_pattern_get(pattern, C.byref(n), C.byref(nnz), C.byref(rp), C.byref(ci)),
+               "lfem_pattern_get")
+    return n.value, nnz.value, rp.value, ci.value
+
+
+_hip = None
+
+
+def copy_from_device(dst: torch.Tensor, src_address: int, nbytes: int):
+    """Device-to-device copy of library-owned memory into a torch tensor."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    if nbytes == 0:
+        return dst
+    assert dst.is_cuda and dst.is_contiguous() and dst.numel() * dst.element_size() >= nbytes
+    torch.cuda.current_stream().synchronize()
+    st = _hip.hipMemcpy(C.c_void_p(dst.data_ptr()), C.c_void_p(src_address), nbytes, 3)
+    if st != 0:
+        raise RuntimeError(f"hipMemcpy failed: {st}")
+    return dst
+
+
+def lfem_assemble(mesh, pattern, what: int, coef_a=None, coef_c=None, vals_m=None, vals_a=None,
+                  vals_mc=None, scatter: int = LFEM_SCATTER_AUTO, stream=None):
+    st = _L.lfem_assemble(mesh, pattern, int(what), _ptr(coef_a, torch.float64, "coef_a"),
+                          _ptr(coef_c, torch.float64, "coef_c"),
+                          _ptr(vals_m, torch.float64, "vals_m"),
+                          _ptr(vals_a, torch.float64, "vals_a"),
+                          _ptr(vals_mc, torch.float64, "vals_mc"), int(scatter), _stream(stream))
+    _lib.check(st, "lfem_assemble")
+
+
+def lfem_assemble_mass(mesh, pattern, vals, stream=None):
+    _lib.check(_L.lfem_assemble_mass(mesh, pattern, _ptr(vals, torch.float64, "vals"),
+                                     _stream(stream)), "lfem_assemble_mass")
+
+
+def lfem_assemble_stiffness(mesh, pattern, coef, vals, stream=None):
+    _lib.check(_L.lfem_assemble_stiffness(mesh, pattern, _ptr(coef, torch.float64, "coef"),
+                                          _ptr(vals, torch.float64, "vals"), _stream(stream)),
+               "lfem_assemble_stiffness")
+
+
+def lfem_assemble_weighted(mesh, pattern, coef, vals, stream=None):
+    _lib.check(_L.lfem_assemble_weighted(mesh, pattern, _ptr(coef, torch.float64, "coef"),
+                                         _ptr(vals, torch.float64, "vals"), _stream(stream)),
+               "lfem_assemble_weighted")
+
+
+def lfem_pattern_autotune(mesh, pattern, what: int, stream=None) -> int:
+    v = C.c_int()
+    _lib.check(_L.lfem_pattern_autotune(mesh, pattern, int(what), _stream(stream), C.byref(v)),
+               "lfem_pattern_autotune")
+    return v.value
+
+
+def lfem_batch_create(meshes, patterns, what: int, autotune: int = 0, stream=None):
+    n = len(meshes)
+    ms = (C.c_void_p * n)(*[m.value for m in meshes])
+    ps = (C.c_void_p * n)(*[p.value for p in patterns])
+    out = C.c_void_p()
+    _lib.check(_L.lfem_batch_create(n, ms, ps, int(what), int(autotune), _stream(stream),
+                                    C.byref(out)), "lfem_batch_create")
+    return out
+
+
+def lfem_assemble_batch(batch, vals, stream=None):
+    """vals: flat list of float64 device tensors, mesh-major, M before A."""
+    arr = (C.c_void_p * len(vals))(*[_ptr(v, torch.float64, "vals").value for v in vals])
+    _lib.check(_L.lfem_assemble_batch(batch, arr, _stream(stream)), "lfem_assemble_batch")
+
+
+def lfem_shape_grad(mesh, u, v, alpha, w, z, beta, grad, stream=None):
+    st = _L.lfem_shape_grad(mesh, _ptr(u, torch.float64, "u"), _ptr(v, torch.float64, "v"),
+                            float(alpha), _ptr(w, torch.float64, "w"),
+                            _ptr(z, torch.float64, "z"), float(beta),
+                            _ptr(grad, torch.float64, "grad"), _stream(stream))
+    _lib.check(st, "lfem_shape_grad")
+
+
+def lfem_energy(mesh, u, v, alpha, w, z, beta, J_out, stream=None):
+    st = _L.lfem_energy(mesh, _ptr(u, torch.float64, "u"), _ptr(v, torch.float64, "v"),
+                        float(alpha), _ptr(w, torch.float64, "w"), _ptr(z, torch.float64, "z"),
+                        float(beta), _ptr(J_out, torch.float64, "J_out"), _stream(stream))
+    _lib.check(st, "lfem_energy")
+
+
+def lfem_status_get(mesh) -> int:
+    n = C.c_int64()
+    _lib.check(_L.lfem_status_get(mesh, C.byref(n)), "lfem_status_get")
+    return n.value
+
+
+def lfem_status_reset(mesh, stream=None):
+    _lib.check(_L.lfem_status_reset(mesh, _stream(stream)), "lfem_status_reset")
+
+
+def lfem_last_error() -> str:
+    return _L.lfem_last_error().decode(errors="replace")
+
+
+def lfem_version() -> str:
+    return _L.lfem_version().decode()
+
+
+def lfem_mesh_destroy(mesh):
+    _L.lfem_mesh_destroy(mesh)
+
+
+def lfem_pattern_destroy(pattern):
+    _L.lfem_pattern_destroy(pattern)
+
+
+def lfem_batch_destroy(batch):
+    _L.lfem_batch_destroy(batch)
+
+
+from .mesh import DeviceMesh, ShapeEnergy  # noqa: E402  (convenience wrappers)
+
+__all__ += ["DeviceMesh", "ShapeEnergy"]

@@ -1,0 +1,267 @@
+// Energy J(x) = alpha u^T A(x) v + beta w^T M(x) z and its shape derivative.
+//
+// Per element and quadrature point, with g_u = sum_a u_a grad_hat phi_a,
+// K = G^{-1}, G = J^T J (the quadrature forms of section 3.2.2):
+//   alpha w mu g_u^T K g_v + beta w mu w_h z_h
+// The derivative of that term with respect to node a, coordinate c follows
+// from d mu = mu (grad phi_a)_c and d(G^{-1}) = -G^{-1} dG G^{-1} for the
+// move dJ = e_c (grad_hat phi_a)^T:
+//   w mu [ alpha ((grad u . grad v) grad phi_a - (grad phi_a . grad u) grad v
+//                 - (grad phi_a . grad v) grad u) + beta w_h z_h grad phi_a ]_c
+// with grad f = J K g_f.  Writing K_a = K g_a, K_u = K g_u, K_v = K g_v this is
+//   w mu J [ (alpha g_u.K_v + beta w_h z_h) K_a - alpha (g_a.K_u) K_v
+//            - alpha (g_a.K_v) K_u ].
+// Element contributions are staged per (local node, component) and gathered
+// per node over its ascending incidence list, so the result is bitwise
+// reproducible.
+#include <cmath>
+
+#include "element.hpp"
+#include "lfem_internal.hpp"
+
+namespace lfem {
+
+namespace {
+
+// GRAD = false: per-element energy into out[e]
+// GRAD = true:  per (local node a, component c) contributions into out[(a*n+c)*T + e]
+template <class E, bool GRAD>
+__global__ __launch_bounds__(256) void k_adjoint(
+    const double *__restrict__ coords, const int32_t *__restrict__ conn,
+    const double *__restrict__ tab, int64_t N, int64_t T, int Q, const double *__restrict__ u,
+    const double *__restrict__ v, double alpha, const double *__restrict__ w,
+    const double *__restrict__ z, double beta, double *__restrict__ out,
+    unsigned long long *__restrict__ degenerate)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    const bool has_a = u && v && alpha != 0.0;
+    const bool has_m = w && z && beta != 0.0;
+    int32_t nid[E::k];
+    double x[E::n][E::k], ue[E::k], ve[E::k], we[E::k], ze[E::k];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) {
+        nid[a] = conn[a * T + e];
+#pragma unroll
+        for (int c = 0; c < E::n; ++c) x[c][a] = coords[c * N + nid[a]];
+        ue[a] = has_a ? u[nid[a]] : 0.0;
+        ve[a] = has_a ? v[nid[a]] : 0.0;
+        we[a] = has_m ? w[nid[a]] : 0.0;
+        ze[a] = has_m ? z[nid[a]] : 0.0;
+    }
+    double energy = 0.0;
+    double acc[E::k][E::n];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a)
+#pragma unroll
+        for (int c = 0; c < E::n; ++c) acc[a][c] = 0.0;
+    int bad = 0;
+    for (int q = 0; q < Q; ++q) {
+        const double *__restrict__ t = tab + q * E::stride;
+        double J[E::n][E::d];
+#pragma unroll
+        for (int c = 0; c < E::n; ++c)
+#pragma unroll
+            for (int m = 0; m < E::d; ++m) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < E::k; ++a) s = fma(x[c][a], t[E::off_g + a * E::d + m], s);
+                J[c][m] = s;
+            }
+        double K[E::d][E::d], mu;
+        geometry<E>(J, K, mu);
+        bad += !(mu > 0.0 && mu < INFINITY);
+        const double wmu = t[0] * mu;
+        double gu[E::d], gv[E::d], wh = 0.0, zh = 0.0;
+#pragma unroll
+        for (int m = 0; m < E::d; ++m) {
+            gu[m] = 0.0;
+            gv[m] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < E::k; ++a) {
+#pragma unroll
+            for (int m = 0; m < E::d; ++m) {
+                gu[m] = fma(ue[a], t[E::off_g + a * E::d + m], gu[m]);
+                gv[m] = fma(ve[a], t[E::off_g + a * E::d + m], gv[m]);
+            }
+            wh = fma(we[a], t[1 + a], wh);
+            zh = fma(ze[a], t[1 + a], zh);
+        }
+        double Ku[E::d], Kv[E::d];
+#pragma unroll
+        for (int m = 0; m < E::d; ++m) {
+            Ku[m] = 0.0;
+            Kv[m] = 0.0;
+#pragma unroll
+            for (int l = 0; l < E::d; ++l) {
+                Ku[m] = fma(K[m][l], gu[l], Ku[m]);
+                Kv[m] = fma(K[m][l], gv[l], Kv[m]);
+            }
+        }
+        double uv = 0.0;
+#pragma unroll
+        for (int m = 0; m < E::d; ++m) uv = fma(gu[m], Kv[m], uv);
+        const double wz = wh * zh;
+        if constexpr (!GRAD) {
+            energy += wmu * (alpha * uv + beta * wz);
+        } else {
+            const double s0 = alpha * uv + beta * wz;
+#pragma unroll
+            for (int a = 0; a < E::k; ++a) {
+                double Ka[E::d], pu = 0.0, pv = 0.0;
+#pragma unroll
+                for (int m = 0; m < E::d; ++m) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < E::d; ++l) s = fma(K[m][l], t[E::off_g + a * E::d + l], s);
+                    Ka[m] = s;
+                    pu = fma(t[E::off_g + a * E::d + m], Ku[m], pu);
+                    pv = fma(t[E::off_g + a * E::d + m], Kv[m], pv);
+                }
+                double r[E::d];
+#pragma unroll
+                for (int m = 0; m < E::d; ++m) r[m] = s0 * Ka[m] - alpha * (pu * Kv[m] + pv * Ku[m]);
+#pragma unroll
+                for (int c = 0; c < E::n; ++c) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int m = 0; m < E::d; ++m) s = fma(J[c][m], r[m], s);
+                    acc[a][c] = fma(wmu, s, acc[a][c]);
+                }
+            }
+        }
+    }
+    if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));
+    if constexpr (!GRAD) {
+        out[e] = energy;
+    } else {
+#pragma unroll
+        for (int a = 0; a < E::k; ++a)
+#pragma unroll
+            for (int c = 0; c < E::n; ++c) out[(a * E::n + c) * T + e] = acc[a][c];
+    }
+}
+
+// grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*n+c)*T + e]
+__global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
+                                                const int32_t *__restrict__ ne_ptr,
+                                                const int32_t *__restrict__ ne,
+                                                const double *__restrict__ stage,
+                                                double *__restrict__ grad)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int32_t s = ne_ptr[r]; s < ne_ptr[r + 1]; ++s) {
+        const int32_t inc = ne[s];
+        const int64_t e = inc >> 4;
+        const int a = inc & 15;
+        for (int c = 0; c < n; ++c) acc[c] += stage[(a * n + c) * T + e];
+    }
+    for (int c = 0; c < n; ++c) grad[c * N + r] = acc[c];
+}
+
+constexpr int RED_NT = 256;
+
+// fixed-order reduction: block b sums x[b*chunk .. (b+1)*chunk) with a
+// strided per-thread loop and an LDS tree
+__global__ __launch_bounds__(RED_NT) void k_reduce_sum(const double *__restrict__ x, int64_t n,
+                                                       int64_t chunk, double *__restrict__ out)
+{
+    __shared__ double s[RED_NT];
+    const int t = threadIdx.x;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t b1 = min(b0 + chunk, n);
+    double acc = 0.0;
+    for (int64_t i = b0 + t; i < b1; i += RED_NT) acc += x[i];
+    s[t] = acc;
+    __syncthreads();
+    for (int w = RED_NT / 2; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[blockIdx.x] = s[0];
+}
+
+inline unsigned grid_for(int64_t n, int nt) { return static_cast<unsigned>((n + nt - 1) / nt); }
+
+template <class E>
+void run_adj(Mesh &m, bool grad, const double *u, const double *v, double alpha, const double *w,
+             const double *z, double beta, double *out, hipStream_t s)
+{
+    if (m.T == 0) return;
+    if (grad)
+        k_adjoint<E, true><<<grid_for(m.T, 256), 256, 0, s>>>(m.coords, m.conn, m.tab, m.N, m.T, m.Q,
+                                                              u, v, alpha, w, z, beta, out,
+                                                              m.degenerate);
+    else
+        k_adjoint<E, false><<<grid_for(m.T, 256), 256, 0, s>>>(m.coords, m.conn, m.tab, m.N, m.T, m.Q,
+                                                               u, v, alpha, w, z, beta, out,
+                                                               m.degenerate);
+    LFEM_HIP(hipGetLastError());
+}
+
+void dispatch(Mesh &m, bool grad, const double *u, const double *v, double alpha, const double *w,
+              const double *z, double beta, double *out, hipStream_t s)
+{
+    switch (m.etype) {
+    case S1P1: run_adj<ET<1, 1, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S1P2: run_adj<ET<1, 1, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S2P1: run_adj<ET<1, 2, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S2P2: run_adj<ET<1, 2, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B2P1: run_adj<ET<0, 2, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B2P2: run_adj<ET<0, 2, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B3P1: run_adj<ET<0, 3, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B3P2: run_adj<ET<0, 3, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    default: throw Error{LFEM_EUNSUPPORTED, "element type"};
+    }
+}
+
+}  // namespace
+
+double *mesh_scratch(Mesh &m, size_t bytes)
+{
+    if (m.scratch_bytes < bytes) {
+        dev_free(m.scratch);
+        m.scratch = nullptr;
+        m.scratch_bytes = 0;
+        LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m.scratch), bytes));
+        m.scratch_bytes = bytes;
+    }
+    return m.scratch;
+}
+
+void launch_energy(Mesh &m, const double *u, const double *v, double alpha, const double *w,
+                   const double *z, double beta, double *J, hipStream_t s)
+{
+    const int64_t chunk = 64 * 1024;
+    const int64_t nblk = std::max<int64_t>(1, (m.T + chunk - 1) / chunk);
+    double *buf = mesh_scratch(m, static_cast<size_t>(m.T + nblk + 1) * sizeof(double));
+    double *part = buf + m.T;
+    if (m.T == 0) {
+        k_reduce_sum<<<1, RED_NT, 0, s>>>(buf, 0, chunk, J);
+        LFEM_HIP(hipGetLastError());
+        return;
+    }
+    dispatch(m, false, u, v, alpha, w, z, beta, buf, s);
+    k_reduce_sum<<<static_cast<unsigned>(nblk), RED_NT, 0, s>>>(buf, m.T, chunk, part);
+    LFEM_HIP(hipGetLastError());
+    k_reduce_sum<<<1, RED_NT, 0, s>>>(part, nblk, nblk, J);
+    LFEM_HIP(hipGetLastError());
+}
+
+void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
+                       const double *w, const double *z, double beta, double *grad,
+                       hipStream_t s)
+{
+    const size_t cnt = static_cast<size_t>(m.k) * m.namb * m.T;
+    double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
+    dispatch(m, true, u, v, alpha, w, z, beta, stage, s);
+    if (m.N > 0) {
+        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, m.namb, m.ne_ptr, m.ne, stage, grad);
+        LFEM_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace lfem

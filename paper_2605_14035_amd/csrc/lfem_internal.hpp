@@ -1,0 +1,160 @@
+// Internal declarations shared by the translation units of liblfem.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lfem.h"
+
+namespace lfem {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Error {
+    lfem_status code;
+    std::string msg;
+};
+
+#define LFEM_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::lfem::Error{e_ == hipErrorOutOfMemory ? LFEM_ENOMEM : LFEM_EHIP,     \
+                                std::string(#call) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+inline void dev_free(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+#define LFEM_REQUIRE(cond, code, msg)                                                    \
+    do {                                                                                 \
+        if (!(cond)) throw ::lfem::Error{(code), (msg)};                                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// element types: (surface?, manifold dimension d, order p)
+// ---------------------------------------------------------------------------
+enum EType : int { S1P1 = 0, S1P2, S2P1, S2P2, B2P1, B2P2, B3P1, B3P2, NUM_ETYPES };
+
+inline int etype_of(int domain, int d, int p)
+{
+    if (domain == LFEM_SURFACE && d == 1) return p == 1 ? S1P1 : S1P2;
+    if (domain == LFEM_SURFACE && d == 2) return p == 1 ? S2P1 : S2P2;
+    if (domain == LFEM_BULK && d == 2) return p == 1 ? B2P1 : B2P2;
+    if (domain == LFEM_BULK && d == 3) return p == 1 ? B3P1 : B3P2;
+    return -1;
+}
+
+inline int nodes_per_elem(int d, int p) { return p == 1 ? d + 1 : (d + 1) * (d + 2) / 2; }
+
+// Reference data per quadrature point q, `stride` doubles each:
+//   [0]                     weight w_q (weights sum to the reference measure)
+//   [1, 1+k)                phi_a(xi_q)
+//   [1+k, 1+k+k*d)          d phi_a / d xi_m at xi_q, index a*d + m
+//   [1+k+k*d, 1+k+k*d+np)   phi_a phi_b for the np = k(k+1)/2 pairs a <= b
+//                           (upper triangle, row-major)
+struct RefTable {
+    int Q = 0, k = 0, d = 0, stride = 0;
+    std::vector<double> data;
+};
+
+// Builds the table of element type (d, p) with the rule of `npts` points
+// (0 = default).  Returns false if the rule does not exist.
+bool build_ref_table(int d, int p, int npts, RefTable &out);
+int default_rule(int d, int p);
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct Mesh {
+    int domain = 0, d = 0, p = 0, namb = 0, k = 0, etype = -1, Q = 0, tab_stride = 0;
+    int64_t N = 0, T = 0;
+    const double *coords = nullptr;
+    const int32_t *conn = nullptr;
+    int device = 0;
+    double *tab = nullptr;           // device reference table
+    RefTable host_tab;
+    int32_t *ne_ptr = nullptr;       // [N+1] node -> incidence offsets
+    int32_t *ne = nullptr;           // [k*T] incidences e*16 + a, ascending per node
+    int32_t *flags = nullptr;        // [4] device flags: [0] bad index, [1] repeated node
+    unsigned long long *degenerate = nullptr;
+    double *scratch = nullptr;       // adjoint staging, grown on demand
+    size_t scratch_bytes = 0;
+};
+
+struct BlockSchedule {
+    int cap = 0;          // max CSR values per block and matrix (LDS capacity)
+    int nb = 0;           // number of blocks
+    int max_rows = 0;     // max rows in one block
+    int max_elems = 0;    // max elements in one block
+    int nthreads = 256;
+    double halo = 0.0;    // sum of block element counts / T
+    int32_t *row_begin = nullptr;  // [nb+1]
+    int32_t *elem_ptr = nullptr;   // [nb+1]
+    int32_t *elems = nullptr;      // block element lists, sorted by colour then id
+    uint8_t *colors = nullptr;     // colour of each list entry
+};
+
+struct Pattern {
+    Mesh *mesh = nullptr;
+    int64_t nnz = 0;
+    int32_t *row_ptr = nullptr;
+    int32_t *col_idx = nullptr;
+    uint8_t *off8 = nullptr;   // [T][kkp] column offset of (a,b) in row conn[a]
+    int kkp = 0;               // bytes per element (k*k rounded up to 4)
+    int max_row = 0;
+    // staged scatter (built on first use)
+    int32_t *cptr = nullptr;   // [nnz+1]
+    int32_t *clist = nullptr;  // [k*k*T] contributions e*128 + a*k + b, ascending per slot
+    double *stage = nullptr;
+    size_t stage_bytes = 0;
+    // blocked scatter
+    BlockSchedule sched;
+    // host copies kept for rebuilding the schedule
+    std::vector<int32_t> h_row_ptr, h_ne_ptr, h_ne, h_conn;
+    int tuned_variant = LFEM_SCATTER_BLOCKED;
+};
+
+// ---------------------------------------------------------------------------
+// symbolic phase (symbolic.hip)
+// ---------------------------------------------------------------------------
+void build_incidence(Mesh &m, hipStream_t s);
+void build_pattern(Mesh &m, Pattern &p, hipStream_t s);
+void build_staged(Mesh &m, Pattern &p, hipStream_t s);
+void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s);
+void free_schedule(BlockSchedule &b);
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *d_total,
+                        hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// numeric phase (numeric.hip)
+// ---------------------------------------------------------------------------
+struct NumericOut {
+    unsigned what = 0;
+    const double *coef_a = nullptr;
+    const double *coef_c = nullptr;
+    double *vals_m = nullptr, *vals_a = nullptr, *vals_mc = nullptr;
+};
+void launch_numeric(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+void fill_zero(double *x, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// adjoint (adjoint.hip)
+// ---------------------------------------------------------------------------
+void launch_energy(Mesh &m, const double *u, const double *v, double alpha, const double *w,
+                   const double *z, double beta, double *J, hipStream_t s);
+void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
+                       const double *w, const double *z, double beta, double *grad,
+                       hipStream_t s);
+double *mesh_scratch(Mesh &m, size_t bytes);
+
+}  // namespace lfem

@@ -1,0 +1,184 @@
+// Reference-element tables: quadrature rules in closed form and the nodal
+// Lagrange basis evaluated at their points (the precompute step of the
+// paper's assembly functions, section 5.2, and Listing 1 (a)).
+//
+// Rules (weights sum to the reference measure: 1, 1/2, 1/6):
+//   segment      Gauss-Legendre with 2 points (degree 3) and 3 points (degree 5)
+//   triangle     3 points, degree 2: barycentric orbit of (2/3, 1/6, 1/6)
+//                6 points, degree 4: two orbits (a, a, 1-2a) with
+//                a = (8 - sqrt10 +- sqrt(38 - 44 sqrt(2/5))) / 18,
+//                weights (620 +- sqrt(213125 - 53320 sqrt10)) / 3720, times 1/2
+//   tetrahedron  4 points, degree 2: orbit (a,a,a,1-3a), a = (5 - sqrt5)/20
+//                11 points, degree 4: centroid (-148/1875), orbit (1/14 x3, 11/14)
+//                (343/7500), orbit (a, a, 1/2-a, 1/2-a), a = (1 + sqrt(5/14))/4
+//                (56/375); volume-one weights, times 1/6
+// Basis, in barycentric coordinates l_0 = 1 - sum xi, l_i = xi_i: P1 l_i;
+// P2 corners l_i (2 l_i - 1), edge nodes 4 l_i l_j with the edge order
+// segment (0,1); triangle (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2),
+// (0,2), (0,3), (1,3), (2,3).
+#include <cmath>
+
+#include "lfem_internal.hpp"
+
+namespace lfem {
+
+namespace {
+
+struct Rule {
+    std::vector<std::vector<double>> pts;  // reference coordinates
+    std::vector<double> w;
+};
+
+void add_bary(Rule &r, std::initializer_list<double> lam, double w)
+{
+    std::vector<double> l(lam);
+    r.pts.emplace_back(l.begin() + 1, l.end());
+    r.w.push_back(w);
+}
+
+bool make_rule(int d, int npts, Rule &r)
+{
+    r = Rule{};
+    if (d == 1) {
+        if (npts == 2) {
+            double s = 0.5 / std::sqrt(3.0);
+            r.pts = {{0.5 - s}, {0.5 + s}};
+            r.w = {0.5, 0.5};
+            return true;
+        }
+        if (npts == 3) {
+            double s = 0.5 * std::sqrt(0.6);
+            r.pts = {{0.5 - s}, {0.5}, {0.5 + s}};
+            r.w = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+            return true;
+        }
+        return false;
+    }
+    if (d == 2) {
+        if (npts == 3) {
+            const double a = 1.0 / 6.0, b = 2.0 / 3.0, w = 1.0 / 6.0;
+            add_bary(r, {b, a, a}, w);
+            add_bary(r, {a, b, a}, w);
+            add_bary(r, {a, a, b}, w);
+            return true;
+        }
+        if (npts == 6) {
+            const double s10 = std::sqrt(10.0);
+            const double root = std::sqrt(38.0 - 44.0 * std::sqrt(0.4));
+            const double wroot = std::sqrt(213125.0 - 53320.0 * s10);
+            const double a[2] = {(8.0 - s10 + root) / 18.0, (8.0 - s10 - root) / 18.0};
+            const double w[2] = {(620.0 + wroot) / 3720.0 * 0.5, (620.0 - wroot) / 3720.0 * 0.5};
+            for (int o = 0; o < 2; ++o) {
+                const double b = 1.0 - 2.0 * a[o];
+                add_bary(r, {b, a[o], a[o]}, w[o]);
+                add_bary(r, {a[o], b, a[o]}, w[o]);
+                add_bary(r, {a[o], a[o], b}, w[o]);
+            }
+            return true;
+        }
+        return false;
+    }
+    if (d == 3) {
+        if (npts == 4) {
+            const double a = (5.0 - std::sqrt(5.0)) / 20.0, b = 1.0 - 3.0 * a, w = 1.0 / 24.0;
+            add_bary(r, {b, a, a, a}, w);
+            add_bary(r, {a, b, a, a}, w);
+            add_bary(r, {a, a, b, a}, w);
+            add_bary(r, {a, a, a, b}, w);
+            return true;
+        }
+        if (npts == 11) {
+            add_bary(r, {0.25, 0.25, 0.25, 0.25}, -148.0 / 1875.0 / 6.0);
+            const double a1 = 1.0 / 14.0, b1 = 11.0 / 14.0, w1 = 343.0 / 7500.0 / 6.0;
+            add_bary(r, {b1, a1, a1, a1}, w1);
+            add_bary(r, {a1, b1, a1, a1}, w1);
+            add_bary(r, {a1, a1, b1, a1}, w1);
+            add_bary(r, {a1, a1, a1, b1}, w1);
+            const double a2 = 0.25 * (1.0 + std::sqrt(5.0 / 14.0));
+            const double b2 = 0.5 - a2, w2 = 56.0 / 375.0 / 6.0;
+            for (int i = 0; i < 4; ++i)
+                for (int j = i + 1; j < 4; ++j) {
+                    double l[4] = {b2, b2, b2, b2};
+                    l[i] = a2;
+                    l[j] = a2;
+                    add_bary(r, {l[0], l[1], l[2], l[3]}, w2);
+                }
+            return true;
+        }
+        return false;
+    }
+    return false;
+}
+
+const int EDGE_SEG[1][2] = {{0, 1}};
+const int EDGE_TRI[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+const int EDGE_TET[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+// values phi[k] and reference gradients g[k][d] at xi
+void eval_basis(int d, int p, const double *xi, double *phi, double *g)
+{
+    double l[4];
+    double dl[4][3] = {};
+    l[0] = 1.0;
+    for (int m = 0; m < d; ++m) {
+        l[0] -= xi[m];
+        dl[0][m] = -1.0;
+        l[m + 1] = xi[m];
+        dl[m + 1][m] = 1.0;
+    }
+    const int nc = d + 1;
+    for (int i = 0; i < nc; ++i) {
+        if (p == 1) {
+            phi[i] = l[i];
+            for (int m = 0; m < d; ++m) g[i * d + m] = dl[i][m];
+        } else {
+            phi[i] = l[i] * (2.0 * l[i] - 1.0);
+            for (int m = 0; m < d; ++m) g[i * d + m] = (4.0 * l[i] - 1.0) * dl[i][m];
+        }
+    }
+    if (p == 2) {
+        const int ne = d == 1 ? 1 : (d == 2 ? 3 : 6);
+        const int(*E)[2] = d == 1 ? EDGE_SEG : (d == 2 ? EDGE_TRI : EDGE_TET);
+        for (int s = 0; s < ne; ++s) {
+            const int i = E[s][0], j = E[s][1], r = nc + s;
+            phi[r] = 4.0 * l[i] * l[j];
+            for (int m = 0; m < d; ++m) g[r * d + m] = 4.0 * (dl[i][m] * l[j] + l[i] * dl[j][m]);
+        }
+    }
+}
+
+}  // namespace
+
+int default_rule(int d, int p)
+{
+    if (d == 1) return p == 1 ? 2 : 3;
+    if (d == 2) return p == 1 ? 3 : 6;
+    return p == 1 ? 4 : 11;
+}
+
+bool build_ref_table(int d, int p, int npts, RefTable &out)
+{
+    if (npts == 0) npts = default_rule(d, p);
+    Rule r;
+    if (!make_rule(d, npts, r)) return false;
+    const int k = nodes_per_elem(d, p), np = k * (k + 1) / 2;
+    out.Q = npts;
+    out.k = k;
+    out.d = d;
+    out.stride = 1 + k + k * d + np;
+    out.data.assign(static_cast<size_t>(out.stride) * npts, 0.0);
+    for (int q = 0; q < npts; ++q) {
+        double *t = out.data.data() + static_cast<size_t>(q) * out.stride;
+        double phi[10], g[30];
+        eval_basis(d, p, r.pts[q].data(), phi, g);
+        t[0] = r.w[q];
+        for (int a = 0; a < k; ++a) t[1 + a] = phi[a];
+        for (int i = 0; i < k * d; ++i) t[1 + k + i] = g[i];
+        int pi = 0;
+        for (int a = 0; a < k; ++a)
+            for (int b = a; b < k; ++b) t[1 + k + k * d + pi++] = phi[a] * phi[b];
+    }
+    return true;
+}
+
+}  // namespace lfem

@@ -1,0 +1,508 @@
+// Symbolic phase: everything that depends only on the element array.
+//
+//  * node -> element incidence (counting sort; each node's list ascending)
+//  * structural CSR pattern: row i holds every node that shares an element
+//    with node i, ascending (the paper keeps COO triples and lets sparse()
+//    sort them, Listing 1 lines 10-11 and 22; here the pattern is computed
+//    once and reused, as section 4.2 notes FEM packages do)
+//  * slot map: for element e and local pair (a, b) the column offset of
+//    conn[b][e] inside row conn[a][e], one byte each
+//  * staged-scatter contribution lists (slot -> (element, pair), ascending)
+//  * row-block schedule of the blocked scatter (host side)
+#include <algorithm>
+#include <cstring>
+
+#include "lfem_internal.hpp"
+
+namespace lfem {
+
+namespace {
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_TILE = 1024;
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_tile(const TI *__restrict__ in,
+                                                       TO *__restrict__ out, int64_t n,
+                                                       int64_t *__restrict__ sums)
+{
+    __shared__ int64_t s[SCAN_NT];
+    const int t = threadIdx.x;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + t * 4;
+    int64_t v[4], acc = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < n) ? static_cast<int64_t>(in[base + i]) : 0;
+        acc += v[i];
+    }
+    s[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < SCAN_NT; off <<= 1) {
+        const int64_t add = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    int64_t run = s[t] - acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < n) out[base + i] = static_cast<TO>(run);
+        run += v[i];
+    }
+    if (t == SCAN_NT - 1) sums[blockIdx.x] = s[t];
+}
+
+template <typename TO>
+__global__ void k_scan_add(TO *__restrict__ out, int64_t n, const int64_t *__restrict__ offs)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = static_cast<TO>(static_cast<int64_t>(out[i]) + offs[i / SCAN_TILE]);
+}
+
+__global__ void k_copy_total(const int64_t *__restrict__ sums, int64_t *__restrict__ total)
+{
+    *total = sums[0];
+}
+
+template <typename TO>
+__global__ void k_write_last(TO *__restrict__ out, int64_t n, const int64_t *__restrict__ total)
+{
+    out[n] = static_cast<TO>(*total);
+}
+
+// exclusive scan of n values; out[n] (if write_last) and *d_total get the total
+template <typename TI, typename TO>
+void scan_rec(const TI *in, TO *out, int64_t n, int64_t *d_total, hipStream_t s)
+{
+    const int64_t ntiles = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+    int64_t *sums = nullptr;
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&sums), ntiles * sizeof(int64_t), s));
+    k_scan_tile<TI, TO><<<ntiles, SCAN_NT, 0, s>>>(in, out, n, sums);
+    LFEM_HIP(hipGetLastError());
+    if (ntiles > 1) {
+        int64_t *offs = nullptr;
+        LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&offs), ntiles * sizeof(int64_t), s));
+        scan_rec<int64_t, int64_t>(sums, offs, ntiles, d_total, s);
+        k_scan_add<TO><<<(n + 255) / 256, 256, 0, s>>>(out, n, offs);
+        LFEM_HIP(hipGetLastError());
+        LFEM_HIP(hipFreeAsync(offs, s));
+    } else {
+        k_copy_total<<<1, 1, 0, s>>>(sums, d_total);
+        LFEM_HIP(hipGetLastError());
+    }
+    LFEM_HIP(hipFreeAsync(sums, s));
+}
+
+// ---------------------------------------------------------------------------
+// node -> element incidence
+// ---------------------------------------------------------------------------
+__global__ void k_inc_count(const int32_t *__restrict__ conn, int64_t kT, int64_t N,
+                            int32_t *__restrict__ cnt, int32_t *__restrict__ flags)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= kT) return;
+    const int32_t node = conn[i];
+    if (node < 0 || node >= N)
+        atomicOr(&flags[0], 1);
+    else
+        atomicAdd(&cnt[node], 1);
+}
+
+__global__ void k_inc_fill(const int32_t *__restrict__ conn, int64_t kT, int64_t T, int64_t N,
+                           const int32_t *__restrict__ ptr, int32_t *__restrict__ cursor,
+                           int32_t *__restrict__ ne)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= kT) return;
+    const int32_t node = conn[i];
+    if (node < 0 || node >= N) return;
+    const int64_t a = i / T, e = i - a * T;
+    const int32_t pos = atomicAdd(&cursor[node], 1);
+    ne[ptr[node] + pos] = static_cast<int32_t>(e * 16 + a);
+}
+
+// sort every short list [ptr[i], ptr[i+1]) ascending (insertion sort)
+__global__ void k_sort_lists(int64_t n, const int32_t *__restrict__ ptr, int32_t *__restrict__ v)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = ptr[i], e = ptr[i + 1];
+    for (int32_t s = b + 1; s < e; ++s) {
+        const int32_t x = v[s];
+        int32_t t = s - 1;
+        while (t >= b && v[t] > x) {
+            v[t + 1] = v[t];
+            --t;
+        }
+        v[t + 1] = x;
+    }
+}
+
+__global__ void k_validate(const int32_t *__restrict__ conn, int64_t T, int k,
+                           int32_t *__restrict__ flags)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b)
+            if (conn[a * T + e] == conn[b * T + e]) atomicOr(&flags[1], 1);
+}
+
+// ---------------------------------------------------------------------------
+// rows: the sorted set of nodes sharing an element with node i
+// ---------------------------------------------------------------------------
+constexpr int ROW_NT = 64;
+constexpr int ROW_MAX = 255;
+
+template <int FILL>
+__global__ __launch_bounds__(ROW_NT) void k_rows(int64_t N, int k, int64_t T,
+                                                 const int32_t *__restrict__ conn,
+                                                 const int32_t *__restrict__ ne_ptr,
+                                                 const int32_t *__restrict__ ne,
+                                                 int32_t *__restrict__ rowlen,
+                                                 const int32_t *__restrict__ row_ptr,
+                                                 int32_t *__restrict__ col_idx,
+                                                 int32_t *__restrict__ flags)
+{
+    __shared__ int32_t buf[ROW_MAX * ROW_NT];
+    const int t = threadIdx.x;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * ROW_NT + t;
+    if (i >= N) return;  // no barrier below
+    int len = 0;
+    bool overflow = false;
+    for (int32_t s = ne_ptr[i]; s < ne_ptr[i + 1] && !overflow; ++s) {
+        const int64_t e = ne[s] >> 4;
+        for (int b = 0; b < k; ++b) {
+            const int32_t j = conn[b * T + e];
+            int lo = 0, hi = len;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (buf[mid * ROW_NT + t] < j)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < len && buf[lo * ROW_NT + t] == j) continue;
+            if (len == ROW_MAX) {
+                overflow = true;
+                break;
+            }
+            for (int r = len; r > lo; --r) buf[r * ROW_NT + t] = buf[(r - 1) * ROW_NT + t];
+            buf[lo * ROW_NT + t] = j;
+            ++len;
+        }
+    }
+    if (overflow) atomicOr(&flags[2], 1);
+    if (!FILL) {
+        rowlen[i] = len;
+    } else {
+        const int32_t b = row_ptr[i];
+        for (int r = 0; r < len; ++r) col_idx[b + r] = buf[r * ROW_NT + t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// slot map
+// ---------------------------------------------------------------------------
+__global__ void k_offsets(int k, int64_t T, const int32_t *__restrict__ conn,
+                          const int32_t *__restrict__ row_ptr,
+                          const int32_t *__restrict__ col_idx, uint8_t *__restrict__ off8,
+                          int kkp, int32_t *__restrict__ flags)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    uint32_t words[25];
+    for (int w = 0; w < kkp / 4; ++w) words[w] = 0;
+    for (int a = 0; a < k; ++a) {
+        const int32_t row = conn[a * T + e];
+        const int32_t beg = row_ptr[row], end = row_ptr[row + 1];
+        for (int b = 0; b < k; ++b) {
+            const int32_t col = conn[b * T + e];
+            int32_t lo = beg, hi = end;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (col_idx[mid] < col)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo >= end || col_idx[lo] != col) atomicOr(&flags[3], 1);
+            const int slot = a * k + b;
+            words[slot >> 2] |= static_cast<uint32_t>((lo - beg) & 0xff) << (8 * (slot & 3));
+        }
+    }
+    uint32_t *dst = reinterpret_cast<uint32_t *>(off8 + e * kkp);
+    for (int w = 0; w < kkp / 4; ++w) dst[w] = words[w];
+}
+
+// ---------------------------------------------------------------------------
+// staged scatter: slot -> contributions
+// ---------------------------------------------------------------------------
+__global__ void k_contrib_count(int k, int64_t T, const int32_t *__restrict__ conn,
+                                const int32_t *__restrict__ row_ptr,
+                                const uint8_t *__restrict__ off8, int kkp,
+                                int32_t *__restrict__ cnt)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    for (int a = 0; a < k; ++a) {
+        const int32_t rb = row_ptr[conn[a * T + e]];
+        for (int b = 0; b < k; ++b) atomicAdd(&cnt[rb + off8[e * kkp + a * k + b]], 1);
+    }
+}
+
+__global__ void k_contrib_fill(int k, int64_t T, const int32_t *__restrict__ conn,
+                               const int32_t *__restrict__ row_ptr,
+                               const uint8_t *__restrict__ off8, int kkp,
+                               const int32_t *__restrict__ cptr, int32_t *__restrict__ cursor,
+                               int32_t *__restrict__ clist)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    for (int a = 0; a < k; ++a) {
+        const int32_t rb = row_ptr[conn[a * T + e]];
+        for (int b = 0; b < k; ++b) {
+            const int32_t slot = rb + off8[e * kkp + a * k + b];
+            const int32_t pos = atomicAdd(&cursor[slot], 1);
+            clist[cptr[slot] + pos] = static_cast<int32_t>(e * 128 + a * k + b);
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n, int nt) { return static_cast<unsigned>((n + nt - 1) / nt); }
+
+template <typename X>
+X *dev_alloc(size_t count)
+{
+    X *p = nullptr;
+    LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(count, 1) * sizeof(X)));
+    return p;
+}
+
+}  // namespace
+
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *d_total,
+                        hipStream_t s)
+{
+    scan_rec<int32_t, int32_t>(in, out, n, d_total, s);
+    k_write_last<int32_t><<<1, 1, 0, s>>>(out, n, d_total);
+    LFEM_HIP(hipGetLastError());
+}
+
+void build_incidence(Mesh &m, hipStream_t s)
+{
+    const int64_t kT = static_cast<int64_t>(m.k) * m.T;
+    m.ne_ptr = dev_alloc<int32_t>(m.N + 1);
+    m.ne = dev_alloc<int32_t>(kT);
+    int32_t *cnt = nullptr;
+    int64_t *tot = nullptr;
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&cnt), (m.N + 1) * sizeof(int32_t), s));
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&tot), sizeof(int64_t), s));
+    LFEM_HIP(hipMemsetAsync(cnt, 0, (m.N + 1) * sizeof(int32_t), s));
+    LFEM_HIP(hipMemsetAsync(m.flags, 0, 4 * sizeof(int32_t), s));
+    if (kT > 0) {
+        k_inc_count<<<grid_for(kT, 256), 256, 0, s>>>(m.conn, kT, m.N, cnt, m.flags);
+        LFEM_HIP(hipGetLastError());
+    }
+    exclusive_scan_i32(cnt, m.ne_ptr, m.N, tot, s);
+    LFEM_HIP(hipMemsetAsync(cnt, 0, (m.N + 1) * sizeof(int32_t), s));
+    if (kT > 0) {
+        k_inc_fill<<<grid_for(kT, 256), 256, 0, s>>>(m.conn, kT, m.T, m.N, m.ne_ptr, cnt, m.ne);
+        LFEM_HIP(hipGetLastError());
+        k_validate<<<grid_for(m.T, 256), 256, 0, s>>>(m.conn, m.T, m.k, m.flags);
+        LFEM_HIP(hipGetLastError());
+    }
+    if (m.N > 0) {
+        k_sort_lists<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.ne_ptr, m.ne);
+        LFEM_HIP(hipGetLastError());
+    }
+    LFEM_HIP(hipFreeAsync(cnt, s));
+    LFEM_HIP(hipFreeAsync(tot, s));
+}
+
+void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
+{
+    p.mesh = &m;
+    int32_t flags[4] = {0, 0, 0, 0};
+    LFEM_HIP(hipMemcpyAsync(flags, m.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipStreamSynchronize(s));
+    LFEM_REQUIRE(!flags[0], LFEM_EINVAL, "connectivity holds a node id outside [0, n_nodes)");
+    LFEM_REQUIRE(!flags[1], LFEM_EINVAL, "an element lists the same node twice");
+
+    int32_t *rowlen = nullptr;
+    int64_t *tot = nullptr;
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&rowlen), (m.N + 1) * sizeof(int32_t), s));
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&tot), sizeof(int64_t), s));
+    p.row_ptr = dev_alloc<int32_t>(m.N + 1);
+    if (m.N > 0) {
+        k_rows<0><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne,
+                                                           rowlen, nullptr, nullptr, m.flags);
+        LFEM_HIP(hipGetLastError());
+    }
+    exclusive_scan_i32(rowlen, p.row_ptr, m.N, tot, s);
+    int64_t nnz = 0;
+    LFEM_HIP(hipMemcpyAsync(&nnz, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipMemcpyAsync(flags, m.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipStreamSynchronize(s));
+    LFEM_HIP(hipFreeAsync(rowlen, s));
+    LFEM_HIP(hipFreeAsync(tot, s));
+    LFEM_REQUIRE(!flags[2], LFEM_ERANGE, "a CSR row would hold more than 255 entries");
+    LFEM_REQUIRE(nnz < (int64_t(1) << 31), LFEM_ERANGE, "nnz does not fit in int32");
+    p.nnz = nnz;
+    p.col_idx = dev_alloc<int32_t>(nnz);
+    if (m.N > 0) {
+        k_rows<1><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne,
+                                                           nullptr, p.row_ptr, p.col_idx, m.flags);
+        LFEM_HIP(hipGetLastError());
+    }
+    p.kkp = (m.k * m.k + 3) / 4 * 4;
+    p.off8 = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * m.T);
+    if (m.T > 0) {
+        k_offsets<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.col_idx, p.off8,
+                                                     p.kkp, m.flags);
+        LFEM_HIP(hipGetLastError());
+    }
+    // host copies for the block schedule
+    p.h_row_ptr.resize(m.N + 1);
+    p.h_ne_ptr.resize(m.N + 1);
+    p.h_ne.resize(static_cast<size_t>(m.k) * m.T);
+    p.h_conn.resize(static_cast<size_t>(m.k) * m.T);
+    LFEM_HIP(hipMemcpyAsync(p.h_row_ptr.data(), p.row_ptr, (m.N + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipMemcpyAsync(p.h_ne_ptr.data(), m.ne_ptr, (m.N + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+    if (m.T > 0) {
+        LFEM_HIP(hipMemcpyAsync(p.h_ne.data(), m.ne, p.h_ne.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+        LFEM_HIP(hipMemcpyAsync(p.h_conn.data(), m.conn, p.h_conn.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+    }
+    LFEM_HIP(hipMemcpyAsync(flags, m.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipStreamSynchronize(s));
+    LFEM_REQUIRE(!flags[3], LFEM_EHIP, "slot map: a local pair was not found in its row");
+    int max_row = 0;
+    for (int64_t i = 0; i < m.N; ++i)
+        max_row = std::max(max_row, p.h_row_ptr[i + 1] - p.h_row_ptr[i]);
+    p.max_row = max_row;
+}
+
+void build_staged(Mesh &m, Pattern &p, hipStream_t s)
+{
+    if (p.cptr) return;
+    LFEM_REQUIRE(m.T < (int64_t(1) << 24), LFEM_EUNSUPPORTED,
+                 "staged scatter supports at most 2^24 elements");
+    const int64_t kkT = static_cast<int64_t>(m.k) * m.k * m.T;
+    int32_t *cnt = nullptr;
+    int64_t *tot = nullptr;
+    p.cptr = dev_alloc<int32_t>(p.nnz + 1);
+    p.clist = dev_alloc<int32_t>(kkT);
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&cnt), (p.nnz + 1) * sizeof(int32_t), s));
+    LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&tot), sizeof(int64_t), s));
+    LFEM_HIP(hipMemsetAsync(cnt, 0, (p.nnz + 1) * sizeof(int32_t), s));
+    if (m.T > 0) {
+        k_contrib_count<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.off8,
+                                                           p.kkp, cnt);
+        LFEM_HIP(hipGetLastError());
+    }
+    exclusive_scan_i32(cnt, p.cptr, p.nnz, tot, s);
+    LFEM_HIP(hipMemsetAsync(cnt, 0, (p.nnz + 1) * sizeof(int32_t), s));
+    if (m.T > 0) {
+        k_contrib_fill<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.off8,
+                                                          p.kkp, p.cptr, cnt, p.clist);
+        LFEM_HIP(hipGetLastError());
+    }
+    if (p.nnz > 0) {
+        k_sort_lists<<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist);
+        LFEM_HIP(hipGetLastError());
+    }
+    LFEM_HIP(hipFreeAsync(cnt, s));
+    LFEM_HIP(hipFreeAsync(tot, s));
+}
+
+void free_schedule(BlockSchedule &b)
+{
+    dev_free(b.row_begin);
+    dev_free(b.elem_ptr);
+    dev_free(b.elems);
+    dev_free(b.colors);
+    b = BlockSchedule{};
+}
+
+// Host: contiguous row blocks with at most `cap` CSR values and `max_rows`
+// rows; each block lists every element touching one of its rows (halo
+// elements appear in several blocks), greedily coloured so that two elements
+// of one colour share no node, and ordered by colour, then element id.
+void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
+{
+    free_schedule(p.sched);
+    BlockSchedule &b = p.sched;
+    b.cap = cap;
+    LFEM_REQUIRE(p.max_row <= cap, LFEM_EINVAL, "block capacity below the longest row");
+    std::vector<int32_t> rb, ep, el;
+    std::vector<uint8_t> col;
+    rb.push_back(0);
+    ep.push_back(0);
+    std::vector<int32_t> stamp(static_cast<size_t>(m.T), -1);
+    std::vector<uint64_t> used(static_cast<size_t>(m.N), 0);
+    std::vector<int32_t> list;
+    std::vector<std::pair<uint8_t, int32_t>> keyed;
+    const int32_t *rp = p.h_row_ptr.data();
+    const int64_t T = m.T;
+    int64_t total = 0;
+    int32_t r0 = 0;
+    int nb = 0;
+    while (r0 < m.N) {
+        int32_t r1 = r0;
+        while (r1 < m.N && rp[r1 + 1] - rp[r0] <= cap && r1 - r0 < max_rows) ++r1;
+        list.clear();
+        for (int32_t r = r0; r < r1; ++r)
+            for (int32_t q = p.h_ne_ptr[r]; q < p.h_ne_ptr[r + 1]; ++q) {
+                const int32_t e = p.h_ne[q] >> 4;
+                if (stamp[e] != nb) {
+                    stamp[e] = nb;
+                    list.push_back(e);
+                }
+            }
+        std::sort(list.begin(), list.end());
+        keyed.clear();
+        for (int32_t e : list) {
+            uint64_t mask = 0;
+            for (int a = 0; a < m.k; ++a) mask |= used[p.h_conn[a * T + e]];
+            LFEM_REQUIRE(~mask != 0, LFEM_EUNSUPPORTED, "block colouring needs more than 64 colours");
+            const int c = __builtin_ctzll(~mask);
+            for (int a = 0; a < m.k; ++a) used[p.h_conn[a * T + e]] |= (uint64_t(1) << c);
+            keyed.emplace_back(static_cast<uint8_t>(c), e);
+        }
+        for (int32_t e : list)
+            for (int a = 0; a < m.k; ++a) used[p.h_conn[a * T + e]] = 0;
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const std::pair<uint8_t, int32_t> &x,
+                            const std::pair<uint8_t, int32_t> &y) { return x.first < y.first; });
+        for (auto &kv : keyed) {
+            el.push_back(kv.second);
+            col.push_back(kv.first);
+        }
+        total += static_cast<int64_t>(keyed.size());
+        b.max_rows = std::max(b.max_rows, static_cast<int>(r1 - r0));
+        b.max_elems = std::max(b.max_elems, static_cast<int>(keyed.size()));
+        rb.push_back(r1);
+        ep.push_back(static_cast<int32_t>(el.size()));
+        r0 = r1;
+        ++nb;
+    }
+    b.nb = nb;
+    b.halo = T > 0 ? static_cast<double>(total) / static_cast<double>(T) : 0.0;
+    b.row_begin = dev_alloc<int32_t>(rb.size());
+    b.elem_ptr = dev_alloc<int32_t>(ep.size());
+    b.elems = dev_alloc<int32_t>(el.size());
+    b.colors = dev_alloc<uint8_t>(col.size());
+    LFEM_HIP(hipMemcpyAsync(b.row_begin, rb.data(), rb.size() * 4, hipMemcpyHostToDevice, s));
+    LFEM_HIP(hipMemcpyAsync(b.elem_ptr, ep.data(), ep.size() * 4, hipMemcpyHostToDevice, s));
+    if (!el.empty()) {
+        LFEM_HIP(hipMemcpyAsync(b.elems, el.data(), el.size() * 4, hipMemcpyHostToDevice, s));
+        LFEM_HIP(hipMemcpyAsync(b.colors, col.data(), col.size(), hipMemcpyHostToDevice, s));
+    }
+    LFEM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace lfem

@@ -1,0 +1,87 @@
+// Autotuner for the numeric scatter: times the deterministic candidates
+// (blocked with several LDS block capacities, staged) on the pattern's own
+// mesh and keeps the fastest.  The atomic variant is never chosen
+// automatically because its summation order is not fixed.
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "lfem_internal.hpp"
+
+namespace lfem {
+
+namespace {
+
+float time_variant(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s)
+{
+    hipEvent_t a, b;
+    LFEM_HIP(hipEventCreate(&a));
+    LFEM_HIP(hipEventCreate(&b));
+    launch_numeric(m, p, o, variant, s);  // warm-up (builds lazy structures)
+    float best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+        LFEM_HIP(hipEventRecord(a, s));
+        launch_numeric(m, p, o, variant, s);
+        LFEM_HIP(hipEventRecord(b, s));
+        LFEM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        LFEM_HIP(hipEventElapsedTime(&ms, a, b));
+        best = std::min(best, ms);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return best;
+}
+
+}  // namespace
+
+int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
+{
+    if (m.T == 0 || p.nnz == 0) return p.tuned_variant;
+    const int nmat = ((what & LFEM_M) ? 1 : 0) + ((what & LFEM_A) ? 1 : 0);
+    double *buf = nullptr;
+    LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&buf), static_cast<size_t>(nmat) * p.nnz * 8));
+    NumericOut o;
+    o.what = what;
+    int slot = 0;
+    if (what & LFEM_M) o.vals_m = buf + static_cast<size_t>(slot++) * p.nnz;
+    if (what & LFEM_A) o.vals_a = buf + static_cast<size_t>(slot++) * p.nnz;
+    float best = 1e30f;
+    int best_variant = LFEM_SCATTER_STAGED, best_cap = 0;
+    try {
+        const int caps[] = {2048, 3072, 4096, 5120};
+        for (int cap : caps) {
+            if (cap < p.max_row) continue;
+            if (static_cast<size_t>(nmat) * cap * 8 + 4 * 1025 > 160 * 1024) continue;
+            try {
+                build_schedule(m, p, cap, 1024, s);
+            } catch (const Error &e) {
+                if (e.code != LFEM_EUNSUPPORTED) throw;
+                continue;
+            }
+            const float t = time_variant(m, p, o, LFEM_SCATTER_BLOCKED, s);
+            if (t < best) {
+                best = t;
+                best_variant = LFEM_SCATTER_BLOCKED;
+                best_cap = cap;
+            }
+        }
+        if (m.T < (int64_t(1) << 24)) {
+            const float t = time_variant(m, p, o, LFEM_SCATTER_STAGED, s);
+            if (t < best) {
+                best = t;
+                best_variant = LFEM_SCATTER_STAGED;
+            }
+        }
+        if (best_variant == LFEM_SCATTER_BLOCKED) build_schedule(m, p, best_cap, 1024, s);
+    } catch (...) {
+        dev_free(buf);
+        throw;
+    }
+    LFEM_HIP(hipStreamSynchronize(s));
+    dev_free(buf);
+    p.tuned_variant = best_variant;
+    return best_variant;
+}
+
+}  // namespace lfem

@@ -1,0 +1,125 @@
+"""Convenience wrappers over the C ABI: a mesh handle that keeps its device
+tensors alive, and the shape-energy autograd Function.  Argument marshalling
+only; the arithmetic runs in liblfem.so."""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFACE,
+               copy_from_device, lfem_assemble, lfem_energy, lfem_mesh_create,
+               lfem_mesh_destroy, lfem_mesh_set_coords, lfem_pattern_build,
+               lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
+
+
+class DeviceMesh:
+    """A mesh resident in device memory plus its library handles.
+
+    ``coords`` float64 (n_amb, N) and ``conn`` int32 (k, T) tensors are kept
+    referenced for the lifetime of the handle (the library does not copy
+    them)."""
+
+    def __init__(self, domain, dim, order, coords, conn, quad_points=0, device="cuda",
+                 stream=None):
+        self.domain = domain if isinstance(domain, int) else (
+            LFEM_SURFACE if domain == "surface" else LFEM_BULK)
+        self.dim, self.order = int(dim), int(order)
+        self.coords = torch.as_tensor(np.ascontiguousarray(coords), dtype=torch.float64,
+                                      device=device).contiguous()
+        self.conn = torch.as_tensor(np.ascontiguousarray(conn), dtype=torch.int32,
+                                    device=device).contiguous()
+        self.handle = lfem_mesh_create(self.domain, self.dim, self.order, self.coords,
+                                       self.conn, quad_points, stream)
+        self.pattern = None
+        self.nnz = None
+
+    @classmethod
+    def from_dict(cls, m, device="cuda", stream=None):
+        return cls(m["domain"], m["dim"], m["order"], m["coords"], m["conn"],
+                   m.get("quad", 0), device, stream)
+
+    @property
+    def N(self):
+        return self.coords.shape[1]
+
+    @property
+    def T(self):
+        return self.conn.shape[1]
+
+    def build_pattern(self, stream=None):
+        if self.pattern is None:
+            self.pattern = lfem_pattern_build(self.handle, stream)
+            _, self.nnz, _, _ = lfem_pattern_get(self.pattern)
+        return self.pattern
+
+    def pattern_tensors(self):
+        """(row_ptr int32 (N+1,), col_idx int32 (nnz,)) copied out of the pattern."""
+        self.build_pattern()
+        n, nnz, rp, ci = lfem_pattern_get(self.pattern)
+        row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.coords.device)
+        col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.coords.device)
+        copy_from_device(row_ptr, rp, (n + 1) * 4)
+        copy_from_device(col_idx, ci, nnz * 4)
+        return row_ptr, col_idx[:nnz]
+
+    def set_coords(self, coords):
+        coords = coords.contiguous()
+        lfem_mesh_set_coords(self.handle, coords)
+        self.coords = coords
+
+    def assemble(self, what, coef_a=None, coef_c=None, scatter=LFEM_SCATTER_AUTO, out=None,
+                 stream=None):
+        """Returns a dict {"M", "A", "MC"} of float64 value tensors (nnz,)."""
+        self.build_pattern(stream)
+        out = dict(out or {})
+        dev = self.coords.device
+        for bit, key in ((LFEM_M, "M"), (LFEM_A, "A"), (LFEM_MC, "MC")):
+            if what & bit and key not in out:
+                out[key] = torch.empty(self.nnz, dtype=torch.float64, device=dev)
+        lfem_assemble(self.handle, self.pattern, what, coef_a, coef_c, out.get("M"),
+                      out.get("A"), out.get("MC"), scatter, stream)
+        return out
+
+    def degenerate_count(self):
+        return lfem_status_get(self.handle)
+
+    def close(self):
+        if getattr(self, "pattern", None) is not None:
+            lfem_pattern_destroy(self.pattern)
+            self.pattern = None
+        if getattr(self, "handle", None) is not None:
+            lfem_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ShapeEnergy(torch.autograd.Function):
+    """J(x) = alpha u^T A(x) v + beta w^T M(x) z as a differentiable function of
+    the node coordinates x (n_amb, N).  Forward: lfem_energy; backward:
+    lfem_shape_grad.  Gradients with respect to u, v, w, z are not provided."""
+
+    @staticmethod
+    def forward(ctx, x, mesh, u, v, w=None, z=None, alpha=1.0, beta=1.0):
+        x = x.detach().contiguous()
+        mesh.set_coords(x)
+        J = torch.empty(1, dtype=torch.float64, device=x.device)
+        lfem_energy(mesh.handle, u, v, alpha, w, z, beta, J)
+        ctx.mesh = mesh
+        ctx.args = (u, v, w, z, alpha, beta)
+        ctx.save_for_backward(x)
+        return J[0]
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (x,) = ctx.saved_tensors
+        u, v, w, z, alpha, beta = ctx.args
+        ctx.mesh.set_coords(x)
+        g = torch.empty_like(x)
+        lfem_shape_grad(ctx.mesh.handle, u, v, alpha, w, z, beta, g)
+        return (g * gJ, None, None, None, None, None, None, None)

@@ -47,8 +47,9 @@ def test_against_central_differences(t):
         Xp[c, r] += h
         Xm[c, r] -= h
         mp_["coords"], mm_["coords"] = Xp, Xm
-        fd = (oracle.energy(mp_, *args) - oracle.energy(mm_, *args)) / (2 * h)
-        assert abs(g[c, r] - fd) <= 1e-6 * max(abs(fd), 1e-3 * gmax), (r, c, g[c, r], fd)
+        fd = (oracle.energy(mp_, *args, long_double=True)
+              - oracle.energy(mm_, *args, long_double=True)) / (2 * h)
+        assert abs(g[c, r] - fd) <= 1e-7 * max(abs(fd), 1e-3 * gmax), (r, c, g[c, r], fd)
 
 
 @pytest.mark.parametrize("t", meshgen.ALL_TYPES)
