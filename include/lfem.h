@@ -120,6 +120,21 @@ lfem_status lfem_pattern_build(lfem_mesh_t m, void *stream, lfem_pattern_t *out)
 lfem_status lfem_pattern_get(lfem_pattern_t p, int64_t *n_rows, int64_t *nnz,
                              const int32_t **row_ptr, const int32_t **col_idx);
 
+/* Statistics of a pattern and of its blocked-scatter schedule. */
+typedef struct {
+    int64_t n_rows, nnz;
+    int32_t max_row;          /* longest CSR row */
+    int32_t blocks;           /* row blocks of the blocked scatter (0: none) */
+    int32_t block_cap;        /* max values per block and matrix */
+    int32_t max_block_rows;
+    int32_t max_block_elems;
+    int32_t max_colors;       /* colours used inside one block */
+    double halo;              /* element evaluations per element (>= 1) */
+    int32_t scatter;          /* variant used by LFEM_SCATTER_AUTO */
+} lfem_pattern_info_t;
+
+lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
+
 /*
  * Numeric phase, any subset of matrices in one pass over the elements.
  * what: bitwise OR of LFEM_M, LFEM_A, LFEM_MC.  coef_a: nodal coefficient

@@ -24,7 +24,7 @@ __all__ = [
     "LFEM_A", "LFEM_BULK", "LFEM_M", "LFEM_MC", "LFEM_SCATTER_ATOMIC", "LFEM_SCATTER_AUTO",
     "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LfemError",
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
-    "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
+    "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
     "lfem_energy", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
@@ -88,6 +88,12 @@ def lfem_pattern_get(pattern):
     _lib.check(_L.lfem_pattern_get(pattern, C.byref(n), C.byref(nnz), C.byref(rp), C.byref(ci)),
                "lfem_pattern_get")
     return n.value, nnz.value, rp.value, ci.value
+
+
+def lfem_pattern_info(pattern) -> dict:
+    info = _lib.PatternInfo()
+    _lib.check(_L.lfem_pattern_info(pattern, C.byref(info)), "lfem_pattern_info")
+    return {name: getattr(info, name) for name, _ in _lib.PatternInfo._fields_}
 
 
 _hip = None

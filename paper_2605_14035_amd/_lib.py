@@ -37,11 +37,19 @@ STATUS_NAMES = {0: "LFEM_OK", 1: "LFEM_EINVAL", 2: "LFEM_ENOMEM", 3: "LFEM_EHIP"
 # every symbol include/lfem.h declares
 EXPORTS = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
+    "lfem_pattern_info",
     "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
     "lfem_energy", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy",
 ]
+
+
+class PatternInfo(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("nnz", C.c_int64), ("max_row", C.c_int32),
+                ("blocks", C.c_int32), ("block_cap", C.c_int32), ("max_block_rows", C.c_int32),
+                ("max_block_elems", C.c_int32), ("max_colors", C.c_int32), ("halo", C.c_double),
+                ("scatter", C.c_int32)]
 
 
 class LfemError(RuntimeError):
@@ -68,6 +76,7 @@ def load():
     L.lfem_mesh_set_coords.argtypes = [vp, vp]
     L.lfem_pattern_build.argtypes = [vp, vp, vpp]
     L.lfem_pattern_get.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vpp, vpp]
+    L.lfem_pattern_info.argtypes = [vp, C.POINTER(PatternInfo)]
     L.lfem_assemble.argtypes = [vp, vp, cu, vp, vp, vp, vp, vp, ci, vp]
     L.lfem_assemble_mass.argtypes = [vp, vp, vp, vp]
     L.lfem_assemble_stiffness.argtypes = [vp, vp, vp, vp, vp]

@@ -40,10 +40,12 @@ __global__ __launch_bounds__(256) void k_adjoint(
     int32_t nid[E::k];
     double x[E::n][E::k], ue[E::k], ve[E::k], we[E::k], ze[E::k];
 #pragma unroll
-    for (int a = 0; a < E::k; ++a) {
-        nid[a] = conn[a * T + e];
+    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
+    gather_coords<E>(nid, coords, N, x);
+    double J0[E::n][E::d], H[E::n][E::nh > 0 ? E::nh : 1];
+    jacobian_setup<E>(x, J0, H);
 #pragma unroll
-        for (int c = 0; c < E::n; ++c) x[c][a] = coords[c * N + nid[a]];
+    for (int a = 0; a < E::k; ++a) {
         ue[a] = has_a ? u[nid[a]] : 0.0;
         ve[a] = has_a ? v[nid[a]] : 0.0;
         we[a] = has_m ? w[nid[a]] : 0.0;
@@ -59,15 +61,7 @@ __global__ __launch_bounds__(256) void k_adjoint(
     for (int q = 0; q < Q; ++q) {
         const double *__restrict__ t = tab + q * E::stride;
         double J[E::n][E::d];
-#pragma unroll
-        for (int c = 0; c < E::n; ++c)
-#pragma unroll
-            for (int m = 0; m < E::d; ++m) {
-                double s = 0.0;
-#pragma unroll
-                for (int a = 0; a < E::k; ++a) s = fma(x[c][a], t[E::off_g + a * E::d + m], s);
-                J[c][m] = s;
-            }
+        jacobian_at<E>(J0, H, t + E::off_xi, J);
         double K[E::d][E::d], mu;
         geometry<E>(J, K, mu);
         bad += !(mu > 0.0 && mu < INFINITY);
@@ -85,8 +79,8 @@ __global__ __launch_bounds__(256) void k_adjoint(
                 gu[m] = fma(ue[a], t[E::off_g + a * E::d + m], gu[m]);
                 gv[m] = fma(ve[a], t[E::off_g + a * E::d + m], gv[m]);
             }
-            wh = fma(we[a], t[1 + a], wh);
-            zh = fma(ze[a], t[1 + a], zh);
+            wh = fma(we[a], t[E::off_phi + a], wh);
+            zh = fma(ze[a], t[E::off_phi + a], zh);
         }
         double Ku[E::d], Kv[E::d];
 #pragma unroll

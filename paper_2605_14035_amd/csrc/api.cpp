@@ -66,6 +66,7 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 void release_mesh(Mesh &m)
 {
     dev_free(m.tab);
+    dev_free(m.tabp);
     dev_free(m.ne_ptr);
     dev_free(m.ne);
     dev_free(m.flags);
@@ -149,6 +150,9 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->degenerate), sizeof(unsigned long long)));
             LFEM_HIP(hipMemcpyAsync(m->tab, tab.data.data(), tab.data.size() * sizeof(double),
                                     hipMemcpyHostToDevice, S(stream)));
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->tabp), tab.pairs.size() * sizeof(double)));
+            LFEM_HIP(hipMemcpyAsync(m->tabp, tab.pairs.data(), tab.pairs.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, S(stream)));
             LFEM_HIP(hipMemsetAsync(m->degenerate, 0, sizeof(unsigned long long), S(stream)));
             build_incidence(*m, S(stream));
             // the host table must outlive the asynchronous copy
@@ -205,6 +209,23 @@ lfem_status lfem_pattern_get(lfem_pattern_t p, int64_t *n_rows, int64_t *nnz,
         if (nnz) *nnz = p->nnz;
         if (row_ptr) *row_ptr = p->row_ptr;
         if (col_idx) *col_idx = p->col_idx;
+    });
+}
+
+lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(p && info, LFEM_EINVAL, "null argument");
+        info->n_rows = p->mesh->N;
+        info->nnz = p->nnz;
+        info->max_row = p->max_row;
+        info->blocks = p->sched.nb;
+        info->block_cap = p->sched.cap;
+        info->max_block_rows = p->sched.max_rows;
+        info->max_block_elems = p->sched.max_elems;
+        info->max_colors = p->sched.max_colors;
+        info->halo = p->sched.halo;
+        info->scatter = p->tuned_variant;
     });
 }
 

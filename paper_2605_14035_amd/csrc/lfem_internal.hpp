@@ -57,14 +57,21 @@ inline int etype_of(int domain, int d, int p)
 inline int nodes_per_elem(int d, int p) { return p == 1 ? d + 1 : (d + 1) * (d + 2) / 2; }
 
 // Reference data per quadrature point q, `stride` doubles each:
-//   [0]                     weight w_q (weights sum to the reference measure)
-//   [1, 1+k)                phi_a(xi_q)
-//   [1+k, 1+k+k*d)          d phi_a / d xi_m at xi_q, index a*d + m
-//   [1+k+k*d, 1+k+k*d+np)   phi_a phi_b for the np = k(k+1)/2 pairs a <= b
-//                           (upper triangle, row-major)
+//   [0]                         weight w_q (weights sum to the reference measure)
+//   [1, 1+d)                    the point xi_q
+//   [1+d, 1+d+k)                phi_a(xi_q)
+//   [1+d+k, 1+d+k+k*d)          d phi_a / d xi_m at xi_q, index a*d + m
+//   [1+d+k+k*d, ... + np)       phi_a phi_b for the np = k(k+1)/2 pairs a <= b
+//                               (upper triangle, row-major)
+//   [..., ... + np*nsym)        reference stiffness tensor R[p][s] over the
+//                               nsym = d(d+1)/2 slots m <= n of a symmetric d x d K
 struct RefTable {
     int Q = 0, k = 0, d = 0, stride = 0;
     std::vector<double> data;
+    // pair-major copy of the reference tensors: for each pair p (a <= b) the Q values
+    // phi_a phi_b (xi_q), then the Q*nsym values R[q][p][s]
+    int pstride = 0;
+    std::vector<double> pairs;
 };
 
 // Builds the table of element type (d, p) with the rule of `npts` points
@@ -82,6 +89,7 @@ struct Mesh {
     const int32_t *conn = nullptr;
     int device = 0;
     double *tab = nullptr;           // device reference table
+    double *tabp = nullptr;          // device pair-major reference tensors
     RefTable host_tab;
     int32_t *ne_ptr = nullptr;       // [N+1] node -> incidence offsets
     int32_t *ne = nullptr;           // [k*T] incidences e*16 + a, ascending per node
@@ -96,12 +104,24 @@ struct BlockSchedule {
     int nb = 0;           // number of blocks
     int max_rows = 0;     // max rows in one block
     int max_elems = 0;    // max elements in one block
+    int max_colors = 0;   // colours used inside one block
     int nthreads = 256;
     double halo = 0.0;    // sum of block element counts / T
+    int64_t len = 0;      // total length of the block element lists
     int32_t *row_begin = nullptr;  // [nb+1]
-    int32_t *elem_ptr = nullptr;   // [nb+1]
-    int32_t *elems = nullptr;      // block element lists, sorted by colour then id
-    uint8_t *colors = nullptr;     // colour of each list entry
+    int32_t *elem_ptr = nullptr;   // [nb+1] list offsets; lists sorted by colour, then element
+    uint8_t *colors = nullptr;     // [len] colour of each list entry
+    int32_t *bconn = nullptr;      // [k][len] node ids of each list entry
+    uint8_t *boff = nullptr;       // [len][kkp] slot offsets of each list entry
+    int mw = 0;                    // mask words per list entry
+    uint32_t *bmask = nullptr;     // [len][mw] bit a*k+b: target entry has >= 3 contributions
+    bool diag_only = false;        // only diagonal entries have >= 3 contributions
+    bool side_mode = false;        // ordered entries summed from LDS side slots (no colours)
+    int ks = 0;                    // side-slot entries per list entry (k rounded up to even)
+    int max_side = 0;              // side slots in the largest block
+    uint16_t *bside = nullptr;     // [len][ks] side slot of contribution (a, a), 0xffff: none
+    uint32_t *bord = nullptr;      // per ordered entry: (LDS index | count << 16, first slot)
+    int32_t *bord_ptr = nullptr;   // [nb+1] offsets into bord (in records)
 };
 
 struct Pattern {
@@ -122,6 +142,7 @@ struct Pattern {
     // host copies kept for rebuilding the schedule
     std::vector<int32_t> h_row_ptr, h_ne_ptr, h_ne, h_conn;
     int tuned_variant = LFEM_SCATTER_BLOCKED;
+    bool force_general = false;  // use the general blocked kernel even where the factor form applies
 };
 
 // ---------------------------------------------------------------------------

@@ -165,19 +165,42 @@ bool build_ref_table(int d, int p, int npts, RefTable &out)
     out.Q = npts;
     out.k = k;
     out.d = d;
-    out.stride = 1 + k + k * d + np;
+    const int nsym = d * (d + 1) / 2;
+    out.stride = 1 + d + k + k * d + np + np * nsym;
     out.data.assign(static_cast<size_t>(out.stride) * npts, 0.0);
     for (int q = 0; q < npts; ++q) {
         double *t = out.data.data() + static_cast<size_t>(q) * out.stride;
         double phi[10], g[30];
         eval_basis(d, p, r.pts[q].data(), phi, g);
         t[0] = r.w[q];
-        for (int a = 0; a < k; ++a) t[1 + a] = phi[a];
-        for (int i = 0; i < k * d; ++i) t[1 + k + i] = g[i];
+        for (int m = 0; m < d; ++m) t[1 + m] = r.pts[q][m];
+        for (int a = 0; a < k; ++a) t[1 + d + a] = phi[a];
+        for (int i = 0; i < k * d; ++i) t[1 + d + k + i] = g[i];
         int pi = 0;
         for (int a = 0; a < k; ++a)
-            for (int b = a; b < k; ++b) t[1 + k + k * d + pi++] = phi[a] * phi[b];
+            for (int b = a; b < k; ++b) t[1 + d + k + k * d + pi++] = phi[a] * phi[b];
+        // reference stiffness tensor R[p][s], s over (m <= n)
+        double *R = t + 1 + d + k + k * d + np;
+        pi = 0;
+        for (int a = 0; a < k; ++a)
+            for (int b = a; b < k; ++b, ++pi) {
+                int si = 0;
+                for (int m = 0; m < d; ++m)
+                    for (int n = m; n < d; ++n, ++si)
+                        R[pi * nsym + si] = m == n ? g[a * d + m] * g[b * d + m]
+                                                   : g[a * d + m] * g[b * d + n] + g[a * d + n] * g[b * d + m];
+            }
     }
+    out.pstride = npts * (1 + nsym);
+    out.pairs.assign(static_cast<size_t>(out.pstride) * np, 0.0);
+    for (int pi = 0; pi < np; ++pi)
+        for (int q = 0; q < npts; ++q) {
+            const double *t = out.data.data() + static_cast<size_t>(q) * out.stride;
+            double *dst = out.pairs.data() + static_cast<size_t>(pi) * out.pstride;
+            dst[q] = t[1 + d + k + k * d + pi];
+            for (int si = 0; si < nsym; ++si)
+                dst[npts + q * nsym + si] = t[1 + d + k + k * d + np + pi * nsym + si];
+        }
     return true;
 }
 

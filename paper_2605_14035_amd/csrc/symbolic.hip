@@ -269,6 +269,70 @@ __global__ void k_contrib_fill(int k, int64_t T, const int32_t *__restrict__ con
     }
 }
 
+// block-ordered copies of the node ids and slot offsets of every list entry, and
+// a bit per local pair that is set when the target CSR entry receives three or
+// more contributions (mult = contributions per entry)
+__global__ void k_block_gather(int64_t L, int k, int64_t T, const int32_t *__restrict__ elems,
+                               const int32_t *__restrict__ conn, const uint8_t *__restrict__ off8,
+                               int kkp, const int32_t *__restrict__ row_ptr,
+                               const int32_t *__restrict__ mult, int mw,
+                               int32_t *__restrict__ bconn, uint8_t *__restrict__ boff,
+                               uint32_t *__restrict__ bmask)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    const int64_t e = elems[i];
+    for (int a = 0; a < k; ++a) bconn[a * L + i] = conn[a * T + e];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(off8 + e * kkp);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(boff + i * kkp);
+    for (int w = 0; w < kkp / 4; ++w) dst[w] = src[w];
+    uint32_t words[4] = {0, 0, 0, 0};
+    for (int a = 0; a < k; ++a) {
+        const int32_t rb = row_ptr[conn[a * T + e]];
+        for (int b = 0; b < k; ++b) {
+            const int slot = a * k + b;
+            if (mult[rb + off8[e * kkp + slot]] >= 3) words[slot >> 5] |= 1u << (slot & 31);
+        }
+    }
+    for (int w = 0; w < mw; ++w) bmask[i * mw + w] = words[w];
+}
+
+// flag <- 1 if an off-diagonal entry receives three or more contributions
+__global__ void k_offdiag_check(int k, int64_t T, const int32_t *__restrict__ conn,
+                                const int32_t *__restrict__ row_ptr,
+                                const uint8_t *__restrict__ off8, int kkp,
+                                const int32_t *__restrict__ mult, int32_t *__restrict__ flag)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    for (int a = 0; a < k; ++a) {
+        const int32_t rb = row_ptr[conn[a * T + e]];
+        for (int b = 0; b < k; ++b)
+            if (a != b && mult[rb + off8[e * kkp + a * k + b]] >= 3) atomicOr(flag, 1);
+    }
+}
+
+// per row: offset of the diagonal inside the row, and its number of contributions
+__global__ void k_diag_info(int64_t N, const int32_t *__restrict__ row_ptr,
+                            const int32_t *__restrict__ col_idx,
+                            const int32_t *__restrict__ mult, int32_t *__restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t lo = row_ptr[i], hi = row_ptr[i + 1];
+    const int32_t beg = lo;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col_idx[mid] < i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const bool found = lo < row_ptr[i + 1] && col_idx[lo] == i;
+    out[i] = found ? lo - beg : 0;
+    out[N + i] = found ? mult[lo] : 0;
+}
+
 inline unsigned grid_for(int64_t n, int nt) { return static_cast<unsigned>((n + nt - 1) / nt); }
 
 template <typename X>
@@ -423,37 +487,95 @@ void free_schedule(BlockSchedule &b)
 {
     dev_free(b.row_begin);
     dev_free(b.elem_ptr);
-    dev_free(b.elems);
     dev_free(b.colors);
+    dev_free(b.bconn);
+    dev_free(b.boff);
+    dev_free(b.bmask);
+    dev_free(b.bside);
+    dev_free(b.bord);
+    dev_free(b.bord_ptr);
     b = BlockSchedule{};
 }
 
 // Host: contiguous row blocks with at most `cap` CSR values and `max_rows`
 // rows; each block lists every element touching one of its rows (halo
-// elements appear in several blocks), greedily coloured so that two elements
-// of one colour share no node, and ordered by colour, then element id.
+// elements appear in several blocks).
+//
+// Entries that receive at most two contributions are summed in any order (the
+// value starts at +0, 0 + a = a, a + b = b + a).  Entries with three or more
+// need a fixed order:
+//  - side mode (only diagonal entries have >= 3 contributions: curves, surfaces,
+//    planar meshes): lists are in element order; every such diagonal
+//    contribution gets its own LDS side slot, slots of one entry are contiguous
+//    in element order, and the entry is summed from its slots after one barrier;
+//  - colour mode (otherwise): lists are greedily coloured so that two elements
+//    of one colour share no node and ordered by colour, then element id; the
+//    ordered contributions are added one colour at a time.
 void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
 {
     free_schedule(p.sched);
     BlockSchedule &b = p.sched;
     b.cap = cap;
     LFEM_REQUIRE(p.max_row <= cap, LFEM_EINVAL, "block capacity below the longest row");
-    std::vector<int32_t> rb, ep, el;
+    const int64_t T = m.T;
+    const int k = m.k;
+    // contributions per CSR entry, off-diagonal check, diagonal position and count per row
+    int32_t *mult = dev_alloc<int32_t>(p.nnz + 1);
+    int32_t *flag = mult + p.nnz;
+    int32_t *dinfo = dev_alloc<int32_t>(2 * m.N + 1);
+    LFEM_HIP(hipMemsetAsync(mult, 0, (p.nnz + 1) * sizeof(int32_t), s));
+    if (T > 0) {
+        k_contrib_count<<<grid_for(T, 256), 256, 0, s>>>(k, T, m.conn, p.row_ptr, p.off8, p.kkp,
+                                                         mult);
+        LFEM_HIP(hipGetLastError());
+        k_offdiag_check<<<grid_for(T, 256), 256, 0, s>>>(k, T, m.conn, p.row_ptr, p.off8, p.kkp,
+                                                         mult, flag);
+        LFEM_HIP(hipGetLastError());
+    }
+    if (m.N > 0) {
+        k_diag_info<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, p.row_ptr, p.col_idx, mult, dinfo);
+        LFEM_HIP(hipGetLastError());
+    }
+    std::vector<int32_t> hd(2 * m.N);
+    int32_t hflag = 0;
+    LFEM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (m.N > 0)
+        LFEM_HIP(hipMemcpyAsync(hd.data(), dinfo, 2 * m.N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LFEM_HIP(hipStreamSynchronize(s));
+    dev_free(dinfo);
+    const int32_t *dpos = hd.data();         // diagonal's offset inside its row
+    const int32_t *dmul = hd.data() + m.N;   // contributions to the diagonal entry
+    b.side_mode = hflag == 0;
+    b.diag_only = b.side_mode;
+
+    std::vector<int32_t> rb, ep, el, ordp;
     std::vector<uint8_t> col;
+    std::vector<uint16_t> side;       // [len][ks] side slot of (a, a) or 0xffff
+    std::vector<uint32_t> ord;        // per ordered entry: (lds index | count << 16, first slot)
+    const int ks = (k + 1) / 2 * 2;
     rb.push_back(0);
     ep.push_back(0);
-    std::vector<int32_t> stamp(static_cast<size_t>(m.T), -1);
-    std::vector<uint64_t> used(static_cast<size_t>(m.N), 0);
-    std::vector<int32_t> list;
+    ordp.push_back(0);
+    std::vector<int32_t> stamp(static_cast<size_t>(T), -1);
+    std::vector<uint64_t> used(b.side_mode ? 0 : static_cast<size_t>(m.N), 0);
+    std::vector<int32_t> list, first, rank;
     std::vector<std::pair<uint8_t, int32_t>> keyed;
     const int32_t *rp = p.h_row_ptr.data();
-    const int64_t T = m.T;
     int64_t total = 0;
     int32_t r0 = 0;
     int nb = 0;
+    b.max_colors = 1;
     while (r0 < m.N) {
+        // grow the block while its values (plus, in side mode, its side slots) fit
         int32_t r1 = r0;
-        while (r1 < m.N && rp[r1 + 1] - rp[r0] <= cap && r1 - r0 < max_rows) ++r1;
+        int64_t slots = 0;
+        while (r1 < m.N && r1 - r0 < max_rows) {
+            const int64_t add = (b.side_mode && dmul[r1] >= 3) ? dmul[r1] : 0;
+            if (rp[r1 + 1] - rp[r0] + slots + add > cap) break;
+            slots += add;
+            ++r1;
+        }
+        LFEM_REQUIRE(r1 > r0, LFEM_EINVAL, "block capacity below one row and its side slots");
         list.clear();
         for (int32_t r = r0; r < r1; ++r)
             for (int32_t q = p.h_ne_ptr[r]; q < p.h_ne_ptr[r + 1]; ++q) {
@@ -464,45 +586,100 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
                 }
             }
         std::sort(list.begin(), list.end());
-        keyed.clear();
-        for (int32_t e : list) {
-            uint64_t mask = 0;
-            for (int a = 0; a < m.k; ++a) mask |= used[p.h_conn[a * T + e]];
-            LFEM_REQUIRE(~mask != 0, LFEM_EUNSUPPORTED, "block colouring needs more than 64 colours");
-            const int c = __builtin_ctzll(~mask);
-            for (int a = 0; a < m.k; ++a) used[p.h_conn[a * T + e]] |= (uint64_t(1) << c);
-            keyed.emplace_back(static_cast<uint8_t>(c), e);
+        if (b.side_mode) {
+            // side slots of the ordered diagonals of this block, in element order
+            first.assign(r1 - r0, -1);
+            rank.assign(r1 - r0, 0);
+            int32_t nslot = 0;
+            for (int32_t r = r0; r < r1; ++r)
+                if (dmul[r] >= 3) {
+                    first[r - r0] = nslot;
+                    LFEM_REQUIRE(dmul[r] < 256, LFEM_EUNSUPPORTED, "diagonal with >255 contributions");
+                    ord.push_back(static_cast<uint32_t>(rp[r] - rp[r0] + dpos[r]) |
+                                  (static_cast<uint32_t>(dmul[r]) << 16));
+                    ord.push_back(static_cast<uint32_t>(nslot));
+                    nslot += dmul[r];
+                }
+            LFEM_REQUIRE(nslot < 65535 && rp[r1] - rp[r0] < 65536, LFEM_EUNSUPPORTED,
+                         "block too large for 16-bit side slots");
+            b.max_side = std::max(b.max_side, static_cast<int>(nslot));
+            for (int32_t e : list) {
+                el.push_back(e);
+                col.push_back(0);
+                for (int a = 0; a < ks; ++a) {
+                    uint16_t v = 0xffff;
+                    if (a < k) {
+                        const int32_t node = p.h_conn[a * T + e];
+                        if (node >= r0 && node < r1 && first[node - r0] >= 0)
+                            v = static_cast<uint16_t>(first[node - r0] + rank[node - r0]++);
+                    }
+                    side.push_back(v);
+                }
+            }
+            ordp.push_back(static_cast<int32_t>(ord.size() / 2));
+        } else {
+            keyed.clear();
+            for (int32_t e : list) {
+                uint64_t mask = 0;
+                for (int a = 0; a < k; ++a) mask |= used[p.h_conn[a * T + e]];
+                LFEM_REQUIRE(~mask != 0, LFEM_EUNSUPPORTED, "block colouring needs more than 64 colours");
+                const int c = __builtin_ctzll(~mask);
+                for (int a = 0; a < k; ++a) used[p.h_conn[a * T + e]] |= (uint64_t(1) << c);
+                keyed.emplace_back(static_cast<uint8_t>(c), e);
+                b.max_colors = std::max(b.max_colors, c + 1);
+            }
+            for (int32_t e : list)
+                for (int a = 0; a < k; ++a) used[p.h_conn[a * T + e]] = 0;
+            std::stable_sort(keyed.begin(), keyed.end(),
+                             [](const std::pair<uint8_t, int32_t> &x,
+                                const std::pair<uint8_t, int32_t> &y) { return x.first < y.first; });
+            for (auto &kv : keyed) {
+                el.push_back(kv.second);
+                col.push_back(kv.first);
+            }
+            ordp.push_back(0);
         }
-        for (int32_t e : list)
-            for (int a = 0; a < m.k; ++a) used[p.h_conn[a * T + e]] = 0;
-        std::stable_sort(keyed.begin(), keyed.end(),
-                         [](const std::pair<uint8_t, int32_t> &x,
-                            const std::pair<uint8_t, int32_t> &y) { return x.first < y.first; });
-        for (auto &kv : keyed) {
-            el.push_back(kv.second);
-            col.push_back(kv.first);
-        }
-        total += static_cast<int64_t>(keyed.size());
+        total += static_cast<int64_t>(list.size());
         b.max_rows = std::max(b.max_rows, static_cast<int>(r1 - r0));
-        b.max_elems = std::max(b.max_elems, static_cast<int>(keyed.size()));
+        b.max_elems = std::max(b.max_elems, static_cast<int>(list.size()));
         rb.push_back(r1);
         ep.push_back(static_cast<int32_t>(el.size()));
         r0 = r1;
         ++nb;
     }
     b.nb = nb;
+    b.len = static_cast<int64_t>(el.size());
     b.halo = T > 0 ? static_cast<double>(total) / static_cast<double>(T) : 0.0;
     b.row_begin = dev_alloc<int32_t>(rb.size());
     b.elem_ptr = dev_alloc<int32_t>(ep.size());
-    b.elems = dev_alloc<int32_t>(el.size());
     b.colors = dev_alloc<uint8_t>(col.size());
+    b.bconn = dev_alloc<int32_t>(static_cast<size_t>(k) * el.size());
+    b.boff = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * el.size());
+    b.mw = (k * k + 31) / 32;
+    b.bmask = dev_alloc<uint32_t>(static_cast<size_t>(b.mw) * el.size());
+    b.ks = ks;
+    b.bside = dev_alloc<uint16_t>(side.size());
+    b.bord = dev_alloc<uint32_t>(ord.size());
+    b.bord_ptr = dev_alloc<int32_t>(ordp.size());
+    int32_t *elems = dev_alloc<int32_t>(el.size());
     LFEM_HIP(hipMemcpyAsync(b.row_begin, rb.data(), rb.size() * 4, hipMemcpyHostToDevice, s));
     LFEM_HIP(hipMemcpyAsync(b.elem_ptr, ep.data(), ep.size() * 4, hipMemcpyHostToDevice, s));
+    LFEM_HIP(hipMemcpyAsync(b.bord_ptr, ordp.data(), ordp.size() * 4, hipMemcpyHostToDevice, s));
+    if (!side.empty())
+        LFEM_HIP(hipMemcpyAsync(b.bside, side.data(), side.size() * 2, hipMemcpyHostToDevice, s));
+    if (!ord.empty())
+        LFEM_HIP(hipMemcpyAsync(b.bord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
     if (!el.empty()) {
-        LFEM_HIP(hipMemcpyAsync(b.elems, el.data(), el.size() * 4, hipMemcpyHostToDevice, s));
+        LFEM_HIP(hipMemcpyAsync(elems, el.data(), el.size() * 4, hipMemcpyHostToDevice, s));
         LFEM_HIP(hipMemcpyAsync(b.colors, col.data(), col.size(), hipMemcpyHostToDevice, s));
+        k_block_gather<<<grid_for(b.len, 256), 256, 0, s>>>(b.len, k, T, elems, m.conn, p.off8,
+                                                            p.kkp, p.row_ptr, mult, b.mw, b.bconn,
+                                                            b.boff, b.bmask);
+        LFEM_HIP(hipGetLastError());
     }
     LFEM_HIP(hipStreamSynchronize(s));
+    dev_free(elems);
+    dev_free(mult);
 }
 
 }  // namespace lfem

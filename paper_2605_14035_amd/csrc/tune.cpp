@@ -4,6 +4,7 @@
 // automatically because its summation order is not fixed.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "lfem_internal.hpp"
@@ -48,8 +49,11 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
     if (what & LFEM_A) o.vals_a = buf + static_cast<size_t>(slot++) * p.nnz;
     float best = 1e30f;
     int best_variant = LFEM_SCATTER_STAGED, best_cap = 0;
+    // LFEM_TUNE_VERBOSE=1 prints every candidate's time to stderr
+    const char *env = std::getenv("LFEM_TUNE_VERBOSE");
+    const bool verbose = env && env[0] == '1';
     try {
-        const int caps[] = {2048, 3072, 4096, 5120};
+        const int caps[] = {1024, 2048, 3072, 4096, 5120, 6144};
         for (int cap : caps) {
             if (cap < p.max_row) continue;
             if (static_cast<size_t>(nmat) * cap * 8 + 4 * 1025 > 160 * 1024) continue;
@@ -60,6 +64,9 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
                 continue;
             }
             const float t = time_variant(m, p, o, LFEM_SCATTER_BLOCKED, s);
+            if (verbose)
+                std::fprintf(stderr, "[lfem tune] blocked cap %d: %.1f us (blocks %d, halo %.3f)\n",
+                             cap, t * 1e3, p.sched.nb, p.sched.halo);
             if (t < best) {
                 best = t;
                 best_variant = LFEM_SCATTER_BLOCKED;
@@ -68,6 +75,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
         }
         if (m.T < (int64_t(1) << 24)) {
             const float t = time_variant(m, p, o, LFEM_SCATTER_STAGED, s);
+            if (verbose) std::fprintf(stderr, "[lfem tune] staged: %.1f us\n", t * 1e3);
             if (t < best) {
                 best = t;
                 best_variant = LFEM_SCATTER_STAGED;
