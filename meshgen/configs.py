@@ -40,7 +40,8 @@ def _pack(name, domain, dim, order, quad, V, F, **fields):
 # smooth radial displacement r = 1 + 0.2 sum_{l<=4} a_lm Y_lm
 # --------------------------------------------------------------------------
 def real_sph_harm(l: int, m: int, P: np.ndarray) -> np.ndarray:
-    """Real orthonormal spherical harmonic Y_lm at unit vectors P (N, 3)."""
+    """Real orthonormal spherical harmonic Y_lm at unit vectors P (N, 3), via
+    SciPy (reference for the vectorised evaluation below)."""
     theta = np.arccos(np.clip(P[:, 2], -1.0, 1.0))
     phi = np.arctan2(P[:, 1], P[:, 0])
     if m == 0:
@@ -50,14 +51,48 @@ def real_sph_harm(l: int, m: int, P: np.ndarray) -> np.ndarray:
     return s * (np.real(y) if m > 0 else np.imag(y))
 
 
+def real_sph_harm_all(lmax: int, P: np.ndarray):
+    """All real orthonormal Y_lm, l <= lmax, at unit vectors P: dict (l, m) -> values.
+
+    Associated Legendre functions without the Condon-Shortley phase by the
+    standard three-term recurrence; Y_l0 = N_l0 P_l^0, Y_lm = sqrt2 N_lm P_l^m
+    cos(m phi), Y_l,-m = sqrt2 N_lm P_l^m sin(m phi), N_lm^2 = (2l+1)/(4 pi)
+    (l-m)!/(l+m)!  (the same functions as real_sph_harm)."""
+    from math import factorial, pi, sqrt
+    x = np.clip(P[:, 2], -1.0, 1.0)
+    phi = np.arctan2(P[:, 1], P[:, 0])
+    sx = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    out = {}
+    for m in range(lmax + 1):
+        pmm = np.full_like(x, float(np.prod(np.arange(1, 2 * m, 2)) if m > 0 else 1.0)) * sx ** m
+        prev2, prev1 = None, pmm
+        for l in range(m, lmax + 1):
+            if l == m:
+                plm = pmm
+            elif l == m + 1:
+                plm = x * (2 * m + 1) * pmm
+            else:
+                plm = ((2 * l - 1) * x * prev1 - (l + m - 1) * prev2) / (l - m)
+            if l > m:
+                prev2, prev1 = prev1, plm
+            nlm = sqrt((2 * l + 1) / (4 * pi) * factorial(l - m) / factorial(l + m))
+            if m == 0:
+                out[(l, 0)] = nlm * plm
+            else:
+                out[(l, m)] = sqrt(2.0) * nlm * plm * np.cos(m * phi)
+                out[(l, -m)] = sqrt(2.0) * nlm * plm * np.sin(m * phi)
+    return out
+
+
 def sh_coefficients(rng, lmax=4, sigma=0.3):
     return {(l, m): rng.normal(0.0, sigma) for l in range(lmax + 1) for m in range(-l, l + 1)}
 
 
 def sh_radius(P_unit: np.ndarray, coeffs) -> np.ndarray:
+    Y = real_sph_harm_all(max(l for l, _ in coeffs), P_unit)
     r = np.ones(len(P_unit))
     for (l, m), a in coeffs.items():
-        r += 0.2 * a * real_sph_harm(l, m, P_unit)
+        r += 0.2 * a * Y[(l, m)]
     return r
 
 

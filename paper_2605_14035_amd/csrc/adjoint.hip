@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_adjoint(
         for (int c = 0; c < E::n; ++c) acc[a][c] = 0.0;
     int bad = 0;
     for (int q = 0; q < Q; ++q) {
-        const double *__restrict__ t = tab + q * E::stride;
+        cdouble *t = const_table(tab) + q * E::stride;
         double J[E::n][E::d];
         jacobian_at<E>(J0, H, t + E::off_xi, J);
         double K[E::d][E::d], mu;

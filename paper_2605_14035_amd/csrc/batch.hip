@@ -1,23 +1,315 @@
-// Batched multi-mesh assembly (placeholder until the persistent kernel lands).
-#include "lfem_internal.hpp"
+// Batched assembly of many meshes of uneven size in one persistent launch.
+//
+// Every (mesh, row block) pair of the batch is a work item; items are sorted by
+// cost (block element count, largest first).  A persistent grid of as many
+// workgroups as fit on the device at once pulls items from an atomic counter,
+// so large and small meshes share the machine without a launch per mesh.  The
+// counter reset and the persistent kernel are captured once into a HIP graph;
+// each lfem_assemble_batch call replays it.  Per-mesh arguments (including the
+// output pointers) live in a device descriptor array that is rewritten only
+// when the caller's output pointers change.
+//
+// The batch kernel covers the mesh families whose many-contribution entries are
+// diagonal (curves, surfaces, planar meshes: the side-slot form of the blocked
+// scatter); meshes outside that family are rejected.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "blocked.hpp"
 
 struct lfem_batch_s {
     int n = 0;
+    unsigned what = 0;
+    int nmat = 0;
+    std::vector<lfem::Mesh *> meshes;
+    std::vector<lfem::Pattern *> pats;
+    std::vector<lfem::BlockArgs> host_desc;
+    lfem::BlockArgs *pinned = nullptr;  // staging for descriptor uploads
+    lfem::BlockArgs *desc = nullptr;    // device descriptors
+    int2 *items = nullptr;              // device work items (mesh, block)
+    int n_items = 0;
+    int *counter = nullptr;
+    size_t lds = 0;
+    int grid = 0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t upload_done = nullptr;
+    bool uploaded = false;
+    std::vector<double *> last_vals;
+    int cap = 0;
 };
 
 namespace lfem {
 
-lfem_status batch_create(int, Mesh *const *, Pattern *const *, unsigned, int, hipStream_t,
-                         lfem_batch_t *)
+namespace {
+
+constexpr int BATCH_NT = 256;
+
+template <int NM, bool HA>
+__global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict__ desc,
+                                                    const int2 *__restrict__ items, int n_items,
+                                                    int *__restrict__ counter)
 {
-    throw Error{LFEM_EUNSUPPORTED, "batched assembly is not built yet"};
+    extern __shared__ double lds[];
+    __shared__ int cur;
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = cur;
+        __syncthreads();
+        if (it >= n_items) break;  // uniform: every workgroup leaves once the list is drained
+        const int2 w = items[it];
+        const BlockArgs g = desc[w.x];
+        switch (g.etype) {
+        case S1P1: blocked_block<ET<1, 1, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case S1P2: blocked_block<ET<1, 1, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case S2P1: blocked_block<ET<1, 2, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case S2P2: blocked_block<ET<1, 2, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case B2P1: blocked_block<ET<0, 2, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case B2P2: blocked_block<ET<0, 2, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        default: break;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
 }
 
-void batch_run(lfem_batch_t, double *const *, hipStream_t)
+__global__ void k_zero_int(int *p) { *p = 0; }
+
+using BatchKernel = void (*)(const BlockArgs *, const int2 *, int, int *);
+
+BatchKernel pick_kernel(unsigned what)
 {
-    throw Error{LFEM_EUNSUPPORTED, "batched assembly is not built yet"};
+    if (what == LFEM_M) return k_batch<1, false>;
+    if (what == LFEM_A) return k_batch<0, true>;
+    return k_batch<1, true>;
 }
 
-void batch_destroy(lfem_batch_t b) { delete b; }
+bool batch_eligible(const Mesh &m, const Pattern &p)
+{
+    return m.d <= 2 && (m.T == 0 || (p.sched.nb > 0 && p.sched.side_mode));
+}
+
+void release_graph(lfem_batch_s &b)
+{
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+}
+
+// (re)build descriptors, work list, launch shape and the captured graph
+void prepare(lfem_batch_s &b, hipStream_t s)
+{
+    release_graph(b);
+    dev_free(b.desc);
+    dev_free(b.items);
+    b.desc = nullptr;
+    b.items = nullptr;
+    b.host_desc.clear();
+    std::vector<std::pair<int, int2>> work;  // (cost, item)
+    size_t lds = 0;
+    for (int i = 0; i < b.n; ++i) {
+        Mesh &m = *b.meshes[i];
+        Pattern &p = *b.pats[i];
+        b.host_desc.push_back(block_args(m, p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+        if (m.T == 0) continue;
+        lds = std::max(lds, block_lds_bytes(p, b.nmat));
+        std::vector<int32_t> ep(p.sched.nb + 1);
+        LFEM_HIP(hipMemcpy(ep.data(), p.sched.elem_ptr, ep.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost));
+        for (int blk = 0; blk < p.sched.nb; ++blk)
+            work.push_back({ep[blk + 1] - ep[blk], make_int2(i, blk)});
+    }
+    LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "batch block schedule exceeds LDS");
+    std::stable_sort(work.begin(), work.end(),
+                     [](const std::pair<int, int2> &x, const std::pair<int, int2> &y) {
+                         return x.first > y.first;
+                     });
+    std::vector<int2> items;
+    items.reserve(work.size());
+    for (auto &w : work) items.push_back(w.second);
+    b.n_items = static_cast<int>(items.size());
+    b.lds = std::max<size_t>(lds, 8);
+    LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b.desc), sizeof(BlockArgs) * b.n));
+    LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b.items), sizeof(int2) * std::max(1, b.n_items)));
+    if (!items.empty())
+        LFEM_HIP(hipMemcpy(b.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+    BatchKernel kern = pick_kernel(b.what);
+    if (b.lds > 64 * 1024)
+        LFEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(b.lds)));
+    int per_cu = 0, dev = 0;
+    LFEM_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    LFEM_HIP(hipGetDeviceProperties(&prop, dev));
+    LFEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
+                                                          BATCH_NT, b.lds));
+    LFEM_REQUIRE(per_cu > 0, LFEM_EUNSUPPORTED, "batch kernel does not fit on a compute unit");
+    b.grid = std::max(1, std::min(per_cu * prop.multiProcessorCount, std::max(1, b.n_items)));
+    // capture: counter reset (a kernel, not a memset node) + persistent kernel
+    LFEM_HIP(hipStreamBeginCapture(b.capture, hipStreamCaptureModeThreadLocal));
+    k_zero_int<<<1, 1, 0, b.capture>>>(b.counter);
+    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter);
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(b.capture, &g);
+    LFEM_HIP(e1);
+    LFEM_HIP(e2);
+    b.graph = g;
+    LFEM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    b.uploaded = false;
+    b.last_vals.clear();
+    (void)s;
+}
+
+void upload_descriptors(lfem_batch_s &b, double *const *vals, hipStream_t s)
+{
+    std::vector<double *> cur(vals, vals + static_cast<size_t>(b.n) * b.nmat);
+    if (b.uploaded && cur == b.last_vals) return;
+    // the staging buffer may still feed the previous upload
+    if (b.uploaded) LFEM_HIP(hipEventSynchronize(b.upload_done));
+    for (int i = 0; i < b.n; ++i) {
+        BlockArgs g = b.host_desc[i];
+        g.v[0] = g.v[1] = g.v[2] = nullptr;
+        for (int j = 0; j < b.nmat; ++j) g.v[j] = cur[static_cast<size_t>(i) * b.nmat + j];
+        b.pinned[i] = g;
+    }
+    LFEM_HIP(hipMemcpyAsync(b.desc, b.pinned, sizeof(BlockArgs) * b.n, hipMemcpyHostToDevice, s));
+    LFEM_HIP(hipEventRecord(b.upload_done, s));
+    b.last_vals = cur;
+    b.uploaded = true;
+}
+
+float time_batch(lfem_batch_s &b, const std::vector<double *> &vals, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    LFEM_HIP(hipEventCreate(&e0));
+    LFEM_HIP(hipEventCreate(&e1));
+    upload_descriptors(b, vals.data(), s);
+    LFEM_HIP(hipGraphLaunch(b.exec, s));
+    float best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+        LFEM_HIP(hipEventRecord(e0, s));
+        LFEM_HIP(hipGraphLaunch(b.exec, s));
+        LFEM_HIP(hipEventRecord(e1, s));
+        LFEM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        LFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+void rebuild_all(lfem_batch_s &b, int cap, hipStream_t s)
+{
+    for (int i = 0; i < b.n; ++i)
+        if (b.meshes[i]->T > 0) build_schedule(*b.meshes[i], *b.pats[i], std::max(cap, b.pats[i]->max_row), 1024, s);
+}
+
+void autotune_batch(lfem_batch_s &b, hipStream_t s)
+{
+    const char *env = std::getenv("LFEM_TUNE_VERBOSE");
+    const bool verbose = env && env[0] == '1';
+    std::vector<double *> vals(static_cast<size_t>(b.n) * b.nmat, nullptr);
+    std::vector<double *> owned;
+    for (int i = 0; i < b.n; ++i)
+        for (int j = 0; j < b.nmat; ++j) {
+            double *v = nullptr;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&v), std::max<int64_t>(b.pats[i]->nnz, 1) * 8));
+            owned.push_back(v);
+            vals[static_cast<size_t>(i) * b.nmat + j] = v;
+        }
+    float best = 1e30f;
+    int best_cap = 4096;
+    try {
+        const int caps[] = {2048, 3072, 4096};
+        for (int cap : caps) {
+            rebuild_all(b, cap, s);
+            bool ok = true;
+            for (int i = 0; i < b.n; ++i) ok = ok && batch_eligible(*b.meshes[i], *b.pats[i]);
+            if (!ok) continue;
+            prepare(b, s);
+            const float t = time_batch(b, vals, s);
+            if (verbose) std::fprintf(stderr, "[lfem tune] batch cap %d: %.1f us\n", cap, t * 1e3);
+            if (t < best) {
+                best = t;
+                best_cap = cap;
+            }
+        }
+    } catch (...) {
+        for (double *v : owned) dev_free(v);
+        throw;
+    }
+    LFEM_HIP(hipStreamSynchronize(s));
+    for (double *v : owned) dev_free(v);
+    rebuild_all(b, best_cap, s);
+    b.cap = best_cap;
+}
+
+}  // namespace
+
+void batch_destroy(lfem_batch_t b);
+
+lfem_status batch_create(int n, Mesh *const *meshes, Pattern *const *pats, unsigned what,
+                         int autotune, hipStream_t s, lfem_batch_t *out)
+{
+    LFEM_REQUIRE(what == LFEM_M || what == LFEM_A || what == (LFEM_M | LFEM_A), LFEM_EINVAL,
+                 "batched assembly supports LFEM_M, LFEM_A or both");
+    auto *b = new lfem_batch_s();
+    try {
+        b->n = n;
+        b->what = what;
+        b->nmat = (what & LFEM_M ? 1 : 0) + (what & LFEM_A ? 1 : 0);
+        b->meshes.assign(meshes, meshes + n);
+        b->pats.assign(pats, pats + n);
+        for (int i = 0; i < n; ++i)
+            LFEM_REQUIRE(batch_eligible(*meshes[i], *pats[i]), LFEM_EUNSUPPORTED,
+                         "batched assembly covers curves, surfaces and planar meshes whose "
+                         "many-contribution entries are diagonal");
+        LFEM_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+        LFEM_HIP(hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming));
+        LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b->counter), sizeof(int)));
+        LFEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&b->pinned), sizeof(BlockArgs) * n,
+                               hipHostMallocDefault));
+        if (autotune) autotune_batch(*b, s);
+        prepare(*b, s);
+    } catch (...) {
+        batch_destroy(b);
+        throw;
+    }
+    *out = b;
+    return LFEM_OK;
+}
+
+void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s)
+{
+    for (int i = 0; i < b->n; ++i)
+        for (int j = 0; j < b->nmat; ++j)
+            LFEM_REQUIRE(vals[static_cast<size_t>(i) * b->nmat + j] || b->pats[i]->nnz == 0,
+                         LFEM_EINVAL, "null output in batch");
+    upload_descriptors(*b, vals, s);
+    LFEM_HIP(hipGraphLaunch(b->exec, s));
+}
+
+void batch_destroy(lfem_batch_t b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    release_graph(*b);
+    dev_free(b->desc);
+    dev_free(b->items);
+    dev_free(b->counter);
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    if (b->upload_done) (void)hipEventDestroy(b->upload_done);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
 
 }  // namespace lfem

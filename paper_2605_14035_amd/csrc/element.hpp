@@ -67,6 +67,14 @@ struct ET {
     using B = RefBasis<D, P>;
 };
 
+// Read-only tables are read through the constant address space: uniform loads
+// from it become scalar loads.
+using cdouble = const __attribute__((address_space(4))) double;
+__device__ __forceinline__ cdouble *const_table(const double *p)
+{
+    return (cdouble *)(p);
+}
+
 template <class E>
 __device__ __forceinline__ void gather_coords(const int32_t (&nid)[E::k],
                                               const double *__restrict__ coords, int64_t N,
@@ -120,7 +128,7 @@ __device__ __forceinline__ void jacobian_setup(const double (&x)[E::n][E::k],
 template <class E>
 __device__ __forceinline__ void jacobian_at(const double (&J0)[E::n][E::d],
                                             const double (&H)[E::n][E::nh > 0 ? E::nh : 1],
-                                            const double *__restrict__ xi, double (&J)[E::n][E::d])
+                                            cdouble *xi, double (&J)[E::n][E::d])
 {
 #pragma unroll
     for (int c = 0; c < E::n; ++c)

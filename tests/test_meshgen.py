@@ -84,3 +84,14 @@ def test_small_meshes_valid(t):
     # no repeated node inside an element
     Fs = np.sort(m["conn"].T, axis=1)
     assert np.all(np.diff(Fs, axis=1) > 0)
+
+
+def test_vectorised_spherical_harmonics():
+    from meshgen import configs as cf
+    rng = np.random.default_rng(0)
+    P = rng.normal(size=(500, 3))
+    P /= np.linalg.norm(P, axis=1)[:, None]
+    Y = cf.real_sph_harm_all(4, P)
+    for l in range(5):
+        for m in range(-l, l + 1):
+            assert np.abs(Y[(l, m)] - cf.real_sph_harm(l, m, P)).max() < 1e-12
