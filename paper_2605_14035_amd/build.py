@@ -15,8 +15,10 @@ LIB = os.path.join(HERE, "liblfem.so")
 SOURCES = ["api.cpp", "ref_tables.cpp", "tune.cpp", "symbolic.hip", "numeric.hip", "adjoint.hip",
            "batch.hip"]
 ARCH = os.environ.get("LFEM_ARCH", "gfx950")
+# -ffp-contract=off: no implicit fused multiply-adds; the kernels write every
+# fma they want, so one source gives the same bits wherever it is inlined
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", SRC]
 
 

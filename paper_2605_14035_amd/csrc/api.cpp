@@ -18,7 +18,7 @@ const char *last_error() { return g_last_error.c_str(); }
 
 // defaults of the blocked scatter's schedule
 constexpr int kDefaultCap = 4096;
-constexpr int kMaxRows = 1024;
+constexpr int kMaxRows = kBlockMaxRows;
 
 }  // namespace lfem
 

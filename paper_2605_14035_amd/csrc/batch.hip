@@ -18,7 +18,7 @@
 #include <cstring>
 #include <vector>
 
-#include "blocked.hpp"
+#include "side.hpp"
 
 struct lfem_batch_s {
     int n = 0;
@@ -33,6 +33,7 @@ struct lfem_batch_s {
     int n_items = 0;
     int *counter = nullptr;
     size_t lds = 0;
+    int dump = 0;  // first LDS dump entry (= largest block capacity)
     int grid = 0;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
@@ -47,15 +48,31 @@ namespace lfem {
 
 namespace {
 
-constexpr int BATCH_NT = 256;
+constexpr int BATCH_NT = kSideThreads;
 
+template <class E, int NM, bool HA>
+__device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *lds, int dump)
+{
+    constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
+    SideBlock<E> s;
+    side_load_rec<E>(g, blk, s);
+    side_load_first<E>(g, s);
+    side_load_coords<E>(g, s);
+    if (g.Q == QA) side_block<E, QA, NM, HA, BATCH_NT>(g, s, lds, dump);
+    else side_block<E, QB, NM, HA, BATCH_NT>(g, s, lds, dump);
+}
+
+// LDS: value entries up to the largest block capacity of the batch (`dump`
+// entries of NM + HA doubles), then the dump entries
 template <int NM, bool HA>
 __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict__ desc,
                                                     const int2 *__restrict__ items, int n_items,
-                                                    int *__restrict__ counter)
+                                                    int *__restrict__ counter, int dump)
 {
+    constexpr int NMAT = NM + (HA ? 1 : 0);
     extern __shared__ double lds[];
     __shared__ int cur;
+    for (int i = threadIdx.x; i < NMAT * dump; i += BATCH_NT) lds[i] = 0.0;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
         __syncthreads();
@@ -65,21 +82,20 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict_
         const int2 w = items[it];
         const BlockArgs g = desc[w.x];
         switch (g.etype) {
-        case S1P1: blocked_block<ET<1, 1, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
-        case S1P2: blocked_block<ET<1, 1, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
-        case S2P1: blocked_block<ET<1, 2, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
-        case S2P2: blocked_block<ET<1, 2, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
-        case B2P1: blocked_block<ET<0, 2, 1>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
-        case B2P2: blocked_block<ET<0, 2, 2>, NM, HA, BATCH_NT, true>(g, w.y, lds); break;
+        case S1P1: batch_item<ET<1, 1, 1>, NM, HA>(g, w.y, lds, dump); break;
+        case S1P2: batch_item<ET<1, 1, 2>, NM, HA>(g, w.y, lds, dump); break;
+        case S2P1: batch_item<ET<1, 2, 1>, NM, HA>(g, w.y, lds, dump); break;
+        case S2P2: batch_item<ET<1, 2, 2>, NM, HA>(g, w.y, lds, dump); break;
+        case B2P1: batch_item<ET<0, 2, 1>, NM, HA>(g, w.y, lds, dump); break;
+        case B2P2: batch_item<ET<0, 2, 2>, NM, HA>(g, w.y, lds, dump); break;
         default: break;
         }
-        __syncthreads();  // LDS is reused by the next item
     }
 }
 
 __global__ void k_zero_int(int *p) { *p = 0; }
 
-using BatchKernel = void (*)(const BlockArgs *, const int2 *, int, int *);
+using BatchKernel = void (*)(const BlockArgs *, const int2 *, int, int *, int);
 
 BatchKernel pick_kernel(unsigned what)
 {
@@ -111,19 +127,23 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     b.items = nullptr;
     b.host_desc.clear();
     std::vector<std::pair<int, int2>> work;  // (cost, item)
-    size_t lds = 0;
+    int max_cap = 1, max_row = 0;
     for (int i = 0; i < b.n; ++i) {
         Mesh &m = *b.meshes[i];
         Pattern &p = *b.pats[i];
         b.host_desc.push_back(block_args(m, p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
         if (m.T == 0) continue;
-        lds = std::max(lds, block_lds_bytes(p, b.nmat));
+        max_cap = std::max(max_cap, p.sched.cap);
+        max_row = std::max(max_row, p.max_row);
         std::vector<int32_t> ep(p.sched.nb + 1);
         LFEM_HIP(hipMemcpy(ep.data(), p.sched.elem_ptr, ep.size() * sizeof(int32_t),
                            hipMemcpyDeviceToHost));
         for (int blk = 0; blk < p.sched.nb; ++blk)
             work.push_back({ep[blk + 1] - ep[blk], make_int2(i, blk)});
     }
+    // value entries of the largest block capacity, then the dump entries
+    b.dump = max_cap;
+    const size_t lds = side_lds_bytes(b.nmat, max_cap, max_row);
     LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "batch block schedule exceeds LDS");
     std::stable_sort(work.begin(), work.end(),
                      [](const std::pair<int, int2> &x, const std::pair<int, int2> &y) {
@@ -133,7 +153,7 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     items.reserve(work.size());
     for (auto &w : work) items.push_back(w.second);
     b.n_items = static_cast<int>(items.size());
-    b.lds = std::max<size_t>(lds, 8);
+    b.lds = lds;
     LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b.desc), sizeof(BlockArgs) * b.n));
     LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b.items), sizeof(int2) * std::max(1, b.n_items)));
     if (!items.empty())
@@ -154,7 +174,7 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     // capture: counter reset (a kernel, not a memset node) + persistent kernel
     LFEM_HIP(hipStreamBeginCapture(b.capture, hipStreamCaptureModeThreadLocal));
     k_zero_int<<<1, 1, 0, b.capture>>>(b.counter);
-    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter);
+    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter, b.dump);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipStreamEndCapture(b.capture, &g);
@@ -210,7 +230,7 @@ float time_batch(lfem_batch_s &b, const std::vector<double *> &vals, hipStream_t
 void rebuild_all(lfem_batch_s &b, int cap, hipStream_t s)
 {
     for (int i = 0; i < b.n; ++i)
-        if (b.meshes[i]->T > 0) build_schedule(*b.meshes[i], *b.pats[i], std::max(cap, b.pats[i]->max_row), 1024, s);
+        if (b.meshes[i]->T > 0) build_schedule(*b.meshes[i], *b.pats[i], std::max(cap, b.pats[i]->max_row), kBlockMaxRows, s);
 }
 
 void autotune_batch(lfem_batch_s &b, hipStream_t s)

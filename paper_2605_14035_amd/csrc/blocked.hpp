@@ -152,7 +152,7 @@ __device__ __forceinline__ void scatter_lds(const int32_t (&rb)[E::k], const uin
 // Arguments of the blocked scatter for one mesh (device pointers and sizes).
 struct BlockArgs {
     const double *coords;
-    const double *tab;
+    const double *tab, *tabp;
     int64_t N;
     int Q;
     int etype;
@@ -162,9 +162,10 @@ struct BlockArgs {
     const int32_t *bconn;
     const uint8_t *boff;
     const uint32_t *bmask;
-    const uint16_t *bside;
+    const uint32_t *bnode;
     const uint32_t *bord;
     const int32_t *bord_ptr;
+    const int32_t *brec;
     int64_t blen;
     int nb, cap, max_side;
     double *v[3];
@@ -177,6 +178,7 @@ inline BlockArgs block_args(const Mesh &m, const Pattern &p, const double *cm0, 
     BlockArgs g{};
     g.coords = m.coords;
     g.tab = m.tab;
+    g.tabp = m.tabp;
     g.N = m.N;
     g.Q = m.Q;
     g.etype = m.etype;
@@ -190,9 +192,10 @@ inline BlockArgs block_args(const Mesh &m, const Pattern &p, const double *cm0, 
     g.bconn = p.sched.bconn;
     g.boff = p.sched.boff;
     g.bmask = p.sched.bmask;
-    g.bside = p.sched.bside;
+    g.bnode = p.sched.bnode;
     g.bord = p.sched.bord;
     g.bord_ptr = p.sched.bord_ptr;
+    g.brec = p.sched.brec;
     g.blen = p.sched.len;
     g.nb = p.sched.nb;
     g.cap = p.sched.cap;
@@ -211,9 +214,9 @@ inline size_t block_lds_bytes(const Pattern &p, int nmat)
            static_cast<size_t>(p.sched.max_rows + 1) * sizeof(int32_t);
 }
 
-// One row block (index blk) of mesh g, by a workgroup of NT threads with
-// NMAT * g.cap doubles + row offsets of dynamic LDS.
-template <class E, int NM, bool HA, int NT, bool SIDE>
+// One row block (index blk) of mesh g in colour mode, by a workgroup of NT
+// threads with NMAT * g.cap doubles + row offsets of dynamic LDS.
+template <class E, int NM, bool HA, int NT>
 __device__ __forceinline__ void blocked_block(const BlockArgs &g, const int blk, double *lds)
 {
     const double *__restrict__ coords = g.coords;
@@ -230,9 +233,6 @@ __device__ __forceinline__ void blocked_block(const BlockArgs &g, const int blk,
     const int32_t *__restrict__ bconn = g.bconn;
     const uint8_t *__restrict__ boff = g.boff;
     const uint32_t *__restrict__ bmask = g.bmask;
-    const uint16_t *__restrict__ bside = g.bside;
-    const uint32_t *__restrict__ bord = g.bord;
-    const int32_t *__restrict__ bord_ptr = g.bord_ptr;
     const int64_t blen = g.blen;
     const int cap = g.cap;
     double *__restrict__ v0 = g.v[0];
@@ -242,9 +242,8 @@ __device__ __forceinline__ void blocked_block(const BlockArgs &g, const int blk,
     constexpr int NMAT = NM + (HA ? 1 : 0);
     constexpr int KKP = (E::k * E::k + 3) / 4 * 4;
     constexpr int MW = (E::k * E::k + 31) / 32;
-    constexpr int KS = (E::k + 1) / 2 * 2;
-    // LDS: per matrix a region of cap doubles holding the block's values and, in
-    // side mode, its side slots right after them; then the block's row offsets
+    // LDS: per matrix a region of cap doubles holding the block's values, then
+    // the block's row offsets
     int32_t *rp = reinterpret_cast<int32_t *>(lds + NMAT * cap);
     const int tid = threadIdx.x;
     const int32_t e0 = beptr[blk], e1 = beptr[blk + 1];
@@ -255,26 +254,19 @@ __device__ __forceinline__ void blocked_block(const BlockArgs &g, const int blk,
     int color = -1;
     int32_t nid[E::k];
     uint32_t ow[KKP / 4];
-    uint32_t om[SIDE ? 1 : MW];
-    uint32_t osd[SIDE ? KS / 2 : 1];
+    uint32_t om[MW];
     double x[E::n][E::k];
     auto load_chunk = [&](int32_t idx) {
         color = -1;
         if (idx < e1) {
-            color = SIDE ? 0 : bcol[idx];
+            color = bcol[idx];
 #pragma unroll
             for (int a = 0; a < E::k; ++a) nid[a] = bconn[a * blen + idx];
             const uint32_t *op = reinterpret_cast<const uint32_t *>(boff + static_cast<int64_t>(idx) * KKP);
 #pragma unroll
             for (int w = 0; w < KKP / 4; ++w) ow[w] = op[w];
-            if constexpr (SIDE) {
-                const uint32_t *sp = reinterpret_cast<const uint32_t *>(bside + static_cast<int64_t>(idx) * KS);
 #pragma unroll
-                for (int w = 0; w < KS / 2; ++w) osd[w] = sp[w];
-            } else {
-#pragma unroll
-                for (int w = 0; w < MW; ++w) om[w] = bmask[static_cast<int64_t>(idx) * MW + w];
-            }
+            for (int w = 0; w < MW; ++w) om[w] = bmask[static_cast<int64_t>(idx) * MW + w];
             gather_coords<E>(nid, coords, N, x);
         }
     };
@@ -297,61 +289,17 @@ __device__ __forceinline__ void blocked_block(const BlockArgs &g, const int blk,
                 rb[a] = (nid[a] >= r0 && nid[a] < r1) ? rp[nid[a] - r0] : -1;
             bad += element_local<E, NM, HA>(nid, x, tab, Q, cm0, cm1, ca, LM, LA);
         }
-        if constexpr (SIDE) {
-            // Every contribution except the ordered diagonals goes to LDS at once
-            // (order-free, at most two per entry); ordered diagonal contributions
-            // are stored in their own side slots and summed after the loop.
-            if (color >= 0) {
-#pragma unroll
-                for (int a = 0; a < E::k; ++a) {
-                    if (rb[a] < 0) continue;
-                    const uint32_t sslot = (osd[a >> 1] >> (16 * (a & 1))) & 0xffffu;
-#pragma unroll
-                    for (int b = 0; b < E::k; ++b) {
-                        const int slot = a * E::k + b;
-                        if (a == b && sslot != 0xffffu) {
-#pragma unroll
-                            for (int mat = 0; mat < NMAT; ++mat)
-                                lds[mat * cap + nloc + sslot] = local_value<E, NM, HA>(mat, a, a, LM, LA);
-                            continue;
-                        }
-                        const int32_t li = rb[a] + static_cast<int32_t>((ow[slot >> 2] >> (8 * (slot & 3))) & 0xffu);
-#pragma unroll
-                        for (int mat = 0; mat < NMAT; ++mat)
-                            __hip_atomic_fetch_add(&lds[mat * cap + li], local_value<E, NM, HA>(mat, a, b, LM, LA),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                }
-            }
-        } else {
-            // Entries with at most two contributions: LDS starts at +0, so 0 + a = a
-            // exactly and a + b = b + a -- the result does not depend on the order and
-            // all threads add at once (ds_add_f64, no return).
-            if (color >= 0) scatter_lds<E, NM, HA, false>(rb, ow, om, LM, LA, lds, cap);
-            // Entries with three or more contributions: one colour at a time (elements
-            // of one colour share no node), so their summation order is fixed.
-            const int cfirst = bcol[c0];
-            const int clast = bcol[min(c0 + NT, e1) - 1];
-            for (int c = cfirst; c <= clast; ++c) {
-                __syncthreads();
-                if (color == c) scatter_lds<E, NM, HA, true>(rb, ow, om, LM, LA, lds, cap);
-            }
-        }
-    }
-    if constexpr (SIDE) {
-        // ordered diagonals: sum each entry's side slots in element order
-        __syncthreads();
-        const int32_t o0 = bord_ptr[blk], o1 = bord_ptr[blk + 1];
-        for (int32_t r = o0 + tid; r < o1; r += NT) {
-            const uint32_t w0 = bord[2 * static_cast<int64_t>(r)];
-            const uint32_t first = bord[2 * static_cast<int64_t>(r) + 1];
-            const uint32_t idx = w0 & 0xffffu, cnt = w0 >> 16;
-#pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) {
-                double acc = 0.0;
-                for (uint32_t j = 0; j < cnt; ++j) acc += lds[mat * cap + nloc + first + j];
-                lds[mat * cap + idx] = acc;
-            }
+        // Entries with at most two contributions: LDS starts at +0, so 0 + a = a
+        // exactly and a + b = b + a -- the result does not depend on the order and
+        // all threads add at once (ds_add_f64, no return).
+        if (color >= 0) scatter_lds<E, NM, HA, false>(rb, ow, om, LM, LA, lds, cap);
+        // Entries with three or more contributions: one colour at a time (elements
+        // of one colour share no node), so their summation order is fixed.
+        const int cfirst = bcol[c0];
+        const int clast = bcol[min(c0 + NT, e1) - 1];
+        for (int c = cfirst; c <= clast; ++c) {
+            __syncthreads();
+            if (color == c) scatter_lds<E, NM, HA, true>(rb, ow, om, LM, LA, lds, cap);
         }
     }
     if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));

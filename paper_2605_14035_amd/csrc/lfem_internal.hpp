@@ -117,12 +117,22 @@ struct BlockSchedule {
     uint32_t *bmask = nullptr;     // [len][mw] bit a*k+b: target entry has >= 3 contributions
     bool diag_only = false;        // only diagonal entries have >= 3 contributions
     bool side_mode = false;        // ordered entries summed from LDS side slots (no colours)
-    int ks = 0;                    // side-slot entries per list entry (k rounded up to even)
     int max_side = 0;              // side slots in the largest block
-    uint16_t *bside = nullptr;     // [len][ks] side slot of contribution (a, a), 0xffff: none
+    int max_ord = 0;               // ordered entries in the largest block
+    // side mode: per list entry and node a, (row start of node a inside the
+    // block, 0xffff if the row is outside) | (side slot of contribution (a, a),
+    // 0xffff: none) << 16
+    uint32_t *bnode = nullptr;     // [len][k]
     uint32_t *bord = nullptr;      // per ordered entry: (LDS index | count << 16, first slot)
     int32_t *bord_ptr = nullptr;   // [nb+1] offsets into bord (in records)
+    // side mode: per block {e0, e1, r0, r1, first CSR value, values, o0, o1}
+    // (element list range, row range, value range, ordered-entry range)
+    int32_t *brec = nullptr;       // [nb][8]
 };
+
+// threads of a side-slot workgroup; side-mode blocks hold at most
+// kSideThreads elements for P2 and four times as many for P1
+constexpr int kSideThreads = 256;
 
 struct Pattern {
     Mesh *mesh = nullptr;
@@ -142,8 +152,11 @@ struct Pattern {
     // host copies kept for rebuilding the schedule
     std::vector<int32_t> h_row_ptr, h_ne_ptr, h_ne, h_conn;
     int tuned_variant = LFEM_SCATTER_BLOCKED;
-    bool force_general = false;  // use the general blocked kernel even where the factor form applies
 };
+
+// most rows of one block (row offsets are staged in LDS; the side-slot kernels
+// hold (kBlockMaxRows + 1) / nthreads of them per thread)
+constexpr int kBlockMaxRows = 1024;
 
 // ---------------------------------------------------------------------------
 // symbolic phase (symbolic.hip)

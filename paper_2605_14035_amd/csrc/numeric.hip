@@ -16,11 +16,18 @@
 //             CSR slot sums its contribution list in ascending element order
 //   blocked - one workgroup owns a contiguous block of rows whose values live
 //             in LDS; it recomputes every element touching the block and
-//             adds them colour by colour (elements of one colour share no
-//             node), then writes the block once.  Fixed order.
+//             writes the block once.  Entries with at most two contributions
+//             are added in any order (exact); the others in a fixed order:
+//             from per-contribution side slots summed in element order
+//             (curves, surfaces, planar meshes, where only diagonals have
+//             more), or colour by colour (tetrahedra; elements of one colour
+//             share no node).
 #include <cmath>
 
-#include "blocked.hpp"
+#include <map>
+#include <tuple>
+
+#include "side.hpp"
 
 namespace lfem {
 
@@ -123,11 +130,51 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
     for (int mat = 0; mat < NMAT; ++mat) outs[mat][s] = acc[mat];
 }
 
-template <class E, int NM, bool HA, int NT, bool SIDE>
+template <class E, int NM, bool HA, int NT>
 __global__ __launch_bounds__(NT) void k_blocked(const BlockArgs g)
 {
     extern __shared__ double lds[];
-    blocked_block<E, NM, HA, NT, SIDE>(g, xcd_block(blockIdx.x, g.nb), lds);
+    blocked_block<E, NM, HA, NT>(g, xcd_block(blockIdx.x, g.nb), lds);
+}
+
+// Persistent side-slot kernel: workgroup w handles the blocks whose launch
+// order index is w, w + G, w + 2G, ... (G = gridDim.x, a multiple of 8 when
+// smaller than the block count, so every block of one workgroup lies in the
+// range of its XCD).  The next block's loads overlap the current block's
+// tail: its record and element words are loaded right after the current
+// compute, its coordinates before the current write-out.
+template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
+__global__ __launch_bounds__(NT) void k_side(const BlockArgs g)
+{
+    constexpr int NMAT = NM + (HA ? 1 : 0);
+    extern __shared__ double lds[];
+    for (int i = threadIdx.x; i < NMAT * g.cap; i += NT) lds[i] = 0.0;
+    __syncthreads();
+    int vb = blockIdx.x;
+    SideBlock<E> s;
+    side_load_rec<E>(g, xcd_block(vb, g.nb), s);
+    side_load_first<E>(g, s);
+    side_load_coords<E>(g, s);
+    for (;;) {
+        const int bad = side_compute<E, Q, NM, HA, NT, MULTI>(g, s, lds, g.cap);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+        const int vn = vb + static_cast<int>(gridDim.x);
+        const bool more = vn < g.nb;
+        SideBlock<E> nxt;
+        if (more) {
+            side_load_rec<E>(g, xcd_block(vn, g.nb), nxt);
+            side_load_first<E>(g, nxt);
+        }
+        __syncthreads();
+        side_reduce<E, NMAT, NT>(g, s, lds);
+        if (more) side_load_coords<E>(g, nxt);
+        __syncthreads();
+        side_write<NMAT, NT>(g, s.base, s.nloc, lds);
+        if (!more) break;
+        __syncthreads();
+        s = nxt;
+        vb = vn;
+    }
 }
 
 __global__ void k_fill_zero(double *__restrict__ x, int64_t n)
@@ -166,8 +213,10 @@ Outs arrange(const NumericOut &o)
     return r;
 }
 
-template <class E, int NM, bool HA, int NT, bool SIDE>
+template <class E, int NM, bool HA, int NT>
 void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
+template <class E, int NM, bool HA, int NT>
+void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
 
 template <class E, int NM, bool HA>
 void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
@@ -209,27 +258,85 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
     }
     // blocked
     LFEM_REQUIRE(p.sched.nb > 0, LFEM_EUNSUPPORTED, "pattern has no block schedule");
-    constexpr int NT = 256;
+    constexpr int NT = kSideThreads;
     const bool side = p.sched.side_mode;
-    const size_t lds = block_lds_bytes(p, NMAT);
+    const size_t lds = side ? side_lds_bytes(NMAT, p.sched.cap, p.max_row) : block_lds_bytes(p, NMAT);
     LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "block schedule exceeds LDS");
-    if (side) return launch_blocked<E, NM, HA, NT, true>(m, p, o, lds, s);
-    return launch_blocked<E, NM, HA, NT, false>(m, p, o, lds, s);
+    if (side) {
+        if constexpr (E::d <= 2) return launch_side<E, NM, HA, NT>(m, p, o, lds, s);
+        throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
+    }
+    return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
 }
 
-template <class E, int NM, bool HA, int NT, bool SIDE>
+// allow more than 64 KB of dynamic LDS for kern (once per size increase)
+void allow_lds(const void *kern, size_t lds)
+{
+    static thread_local std::map<const void *, size_t> granted;
+    size_t &g = granted[kern];
+    if (lds > 64 * 1024 && lds > g) {
+        LFEM_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        g = lds;
+    }
+}
+
+// workgroups of kern that are resident on the device at once
+int resident_groups(const void *kern, int nt, size_t lds)
+{
+    static thread_local std::map<std::tuple<const void *, size_t, int>, int> known;
+    int dev = 0;
+    LFEM_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(kern, lds, dev);
+    auto it = known.find(key);
+    if (it != known.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    LFEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
+    LFEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LFEM_REQUIRE(per_cu > 0, LFEM_EUNSUPPORTED, "block kernel does not fit on a compute unit");
+    const int r = per_cu * cus;
+    known.emplace(key, r);
+    return r;
+}
+
+template <class E, int NM, bool HA, int NT>
 void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
 {
-    auto kern = k_blocked<E, NM, HA, NT, SIDE>;
-    static thread_local size_t attr_lds = 64 * 1024;
-    if (lds > attr_lds) {
-        LFEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     static_cast<int>(lds)));
-        attr_lds = lds;
-    }
+    auto kern = k_blocked<E, NM, HA, NT>;
+    allow_lds(reinterpret_cast<const void *>(kern), lds);
     kern<<<p.sched.nb, NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]));
     LFEM_HIP(hipGetLastError());
+}
+
+template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
+void launch_side_q(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
+{
+    auto kern = k_side<E, Q, NM, HA, NT, MULTI>;
+    const void *kp = reinterpret_cast<const void *>(kern);
+    allow_lds(kp, lds);
+    int grid = resident_groups(kp, NT, lds);
+    if (grid >= p.sched.nb) grid = p.sched.nb;
+    else grid &= ~7;  // keep each workgroup on the XCD its block range belongs to
+    kern<<<std::max(grid, 1), NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]));
+    LFEM_HIP(hipGetLastError());
+}
+
+template <class E, int NM, bool HA, int NT>
+void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
+{
+    // the two rules of each dimension (segment 2, 3; triangle 3, 6 points)
+    constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
+    // blocks of more than NT elements (P1 meshes) need the chunk loop
+    const bool multi = p.sched.max_elems > NT;
+    if constexpr (E::p == 1) {
+        if (m.Q == QA) return launch_side_q<E, QA, NM, HA, NT, true>(m, p, o, lds, s);
+        if (m.Q == QB) return launch_side_q<E, QB, NM, HA, NT, true>(m, p, o, lds, s);
+    } else {
+        if (m.Q == QA) return multi ? launch_side_q<E, QA, NM, HA, NT, true>(m, p, o, lds, s)
+                                    : launch_side_q<E, QA, NM, HA, NT, false>(m, p, o, lds, s);
+        if (m.Q == QB) return multi ? launch_side_q<E, QB, NM, HA, NT, true>(m, p, o, lds, s)
+                                    : launch_side_q<E, QB, NM, HA, NT, false>(m, p, o, lds, s);
+    }
+    throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
 }
 
 template <class E>

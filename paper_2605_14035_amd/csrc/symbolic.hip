@@ -491,7 +491,8 @@ void free_schedule(BlockSchedule &b)
     dev_free(b.bconn);
     dev_free(b.boff);
     dev_free(b.bmask);
-    dev_free(b.bside);
+    dev_free(b.bnode);
+    dev_free(b.brec);
     dev_free(b.bord);
     dev_free(b.bord_ptr);
     b = BlockSchedule{};
@@ -513,6 +514,7 @@ void free_schedule(BlockSchedule &b)
 //    ordered contributions are added one colour at a time.
 void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
 {
+    LFEM_REQUIRE(max_rows >= 1 && max_rows <= kBlockMaxRows, LFEM_EINVAL, "rows per block out of range");
     free_schedule(p.sched);
     BlockSchedule &b = p.sched;
     b.cap = cap;
@@ -545,14 +547,15 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
     dev_free(dinfo);
     const int32_t *dpos = hd.data();         // diagonal's offset inside its row
     const int32_t *dmul = hd.data() + m.N;   // contributions to the diagonal entry
-    b.side_mode = hflag == 0;
+    // (tetrahedral meshes always take colour mode: their side-slot kernels would
+    // need the Q-point data of 11 points in registers)
+    b.side_mode = hflag == 0 && m.d <= 2;
     b.diag_only = b.side_mode;
 
-    std::vector<int32_t> rb, ep, el, ordp;
+    std::vector<int32_t> rb, ep, el, ordp, rec;
     std::vector<uint8_t> col;
-    std::vector<uint16_t> side;       // [len][ks] side slot of (a, a) or 0xffff
+    std::vector<uint32_t> node;       // side mode: [len][k] row start | side slot << 16
     std::vector<uint32_t> ord;        // per ordered entry: (lds index | count << 16, first slot)
-    const int ks = (k + 1) / 2 * 2;
     rb.push_back(0);
     ep.push_back(0);
     ordp.push_back(0);
@@ -561,31 +564,40 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
     std::vector<int32_t> list, first, rank;
     std::vector<std::pair<uint8_t, int32_t>> keyed;
     const int32_t *rp = p.h_row_ptr.data();
+    const size_t max_elems = b.side_mode ? static_cast<size_t>(kSideThreads) * (m.p == 1 ? 4 : 1)
+                                         : static_cast<size_t>(T) + 1;
     int64_t total = 0;
     int32_t r0 = 0;
     int nb = 0;
     b.max_colors = 1;
     while (r0 < m.N) {
-        // grow the block while its values (plus, in side mode, its side slots) fit
+        // grow the block while its values (plus, in side mode, its side slots)
+        // fit and, in side mode, its element list stays within max_elems
         int32_t r1 = r0;
         int64_t slots = 0;
+        list.clear();
         while (r1 < m.N && r1 - r0 < max_rows) {
             const int64_t add = (b.side_mode && dmul[r1] >= 3) ? dmul[r1] : 0;
             if (rp[r1 + 1] - rp[r0] + slots + add > cap) break;
-            slots += add;
-            ++r1;
-        }
-        LFEM_REQUIRE(r1 > r0, LFEM_EINVAL, "block capacity below one row and its side slots");
-        list.clear();
-        for (int32_t r = r0; r < r1; ++r)
-            for (int32_t q = p.h_ne_ptr[r]; q < p.h_ne_ptr[r + 1]; ++q) {
+            const size_t before = list.size();
+            for (int32_t q = p.h_ne_ptr[r1]; q < p.h_ne_ptr[r1 + 1]; ++q) {
                 const int32_t e = p.h_ne[q] >> 4;
                 if (stamp[e] != nb) {
                     stamp[e] = nb;
                     list.push_back(e);
                 }
             }
+            if (list.size() > max_elems && r1 > r0) {
+                for (size_t i = before; i < list.size(); ++i) stamp[list[i]] = -1;
+                list.resize(before);
+                break;
+            }
+            slots += add;
+            ++r1;
+        }
+        LFEM_REQUIRE(r1 > r0, LFEM_EINVAL, "block capacity below one row and its side slots");
         std::sort(list.begin(), list.end());
+        const int32_t o0 = static_cast<int32_t>(ord.size() / 2);
         if (b.side_mode) {
             // side slots of the ordered diagonals of this block, in element order
             first.assign(r1 - r0, -1);
@@ -600,20 +612,21 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
                     ord.push_back(static_cast<uint32_t>(nslot));
                     nslot += dmul[r];
                 }
-            LFEM_REQUIRE(nslot < 65535 && rp[r1] - rp[r0] < 65536, LFEM_EUNSUPPORTED,
+            LFEM_REQUIRE(nslot < 65535 && rp[r1] - rp[r0] < 65535, LFEM_EUNSUPPORTED,
                          "block too large for 16-bit side slots");
             b.max_side = std::max(b.max_side, static_cast<int>(nslot));
             for (int32_t e : list) {
                 el.push_back(e);
                 col.push_back(0);
-                for (int a = 0; a < ks; ++a) {
-                    uint16_t v = 0xffff;
-                    if (a < k) {
-                        const int32_t node = p.h_conn[a * T + e];
-                        if (node >= r0 && node < r1 && first[node - r0] >= 0)
-                            v = static_cast<uint16_t>(first[node - r0] + rank[node - r0]++);
+                for (int a = 0; a < k; ++a) {
+                    uint32_t start = 0xffff, slot = 0xffff;
+                    const int32_t nd = p.h_conn[a * T + e];
+                    if (nd >= r0 && nd < r1) {
+                        start = static_cast<uint32_t>(rp[nd] - rp[r0]);
+                        if (first[nd - r0] >= 0)
+                            slot = static_cast<uint32_t>(first[nd - r0] + rank[nd - r0]++);
                     }
-                    side.push_back(v);
+                    node.push_back(start | (slot << 16));
                 }
             }
             ordp.push_back(static_cast<int32_t>(ord.size() / 2));
@@ -637,13 +650,18 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
                 el.push_back(kv.second);
                 col.push_back(kv.first);
             }
-            ordp.push_back(0);
+            ordp.push_back(o0);
         }
+        const int32_t o1 = ordp.back();
+        b.max_ord = std::max(b.max_ord, static_cast<int>(o1 - o0));
+        const int32_t e1 = static_cast<int32_t>(el.size());
+        const int32_t e0 = e1 - static_cast<int32_t>(list.size());
+        rec.insert(rec.end(), {e0, e1, r0, r1, rp[r0], rp[r1] - rp[r0], o0, o1});
         total += static_cast<int64_t>(list.size());
         b.max_rows = std::max(b.max_rows, static_cast<int>(r1 - r0));
         b.max_elems = std::max(b.max_elems, static_cast<int>(list.size()));
         rb.push_back(r1);
-        ep.push_back(static_cast<int32_t>(el.size()));
+        ep.push_back(e1);
         r0 = r1;
         ++nb;
     }
@@ -657,16 +675,17 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
     b.boff = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * el.size());
     b.mw = (k * k + 31) / 32;
     b.bmask = dev_alloc<uint32_t>(static_cast<size_t>(b.mw) * el.size());
-    b.ks = ks;
-    b.bside = dev_alloc<uint16_t>(side.size());
+    b.bnode = dev_alloc<uint32_t>(node.size());
     b.bord = dev_alloc<uint32_t>(ord.size());
     b.bord_ptr = dev_alloc<int32_t>(ordp.size());
+    b.brec = dev_alloc<int32_t>(rec.size());
     int32_t *elems = dev_alloc<int32_t>(el.size());
     LFEM_HIP(hipMemcpyAsync(b.row_begin, rb.data(), rb.size() * 4, hipMemcpyHostToDevice, s));
     LFEM_HIP(hipMemcpyAsync(b.elem_ptr, ep.data(), ep.size() * 4, hipMemcpyHostToDevice, s));
     LFEM_HIP(hipMemcpyAsync(b.bord_ptr, ordp.data(), ordp.size() * 4, hipMemcpyHostToDevice, s));
-    if (!side.empty())
-        LFEM_HIP(hipMemcpyAsync(b.bside, side.data(), side.size() * 2, hipMemcpyHostToDevice, s));
+    LFEM_HIP(hipMemcpyAsync(b.brec, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, s));
+    if (!node.empty())
+        LFEM_HIP(hipMemcpyAsync(b.bnode, node.data(), node.size() * 4, hipMemcpyHostToDevice, s));
     if (!ord.empty())
         LFEM_HIP(hipMemcpyAsync(b.bord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
     if (!el.empty()) {

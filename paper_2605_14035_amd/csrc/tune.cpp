@@ -58,7 +58,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
             if (cap < p.max_row) continue;
             if (static_cast<size_t>(nmat) * cap * 8 + 4 * 1025 > 160 * 1024) continue;
             try {
-                build_schedule(m, p, cap, 1024, s);
+                build_schedule(m, p, cap, kBlockMaxRows, s);
             } catch (const Error &e) {
                 if (e.code != LFEM_EUNSUPPORTED) throw;
                 continue;
@@ -81,7 +81,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
                 best_variant = LFEM_SCATTER_STAGED;
             }
         }
-        if (best_variant == LFEM_SCATTER_BLOCKED) build_schedule(m, p, best_cap, 1024, s);
+        if (best_variant == LFEM_SCATTER_BLOCKED) build_schedule(m, p, best_cap, kBlockMaxRows, s);
     } catch (...) {
         dev_free(buf);
         throw;
