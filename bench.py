@@ -30,9 +30,15 @@ METRIC = "elements/s for M+A assembly (P2 surface), % HBM roofline, batched vs p
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
 
+KERNEL_SOURCES = ("numeric.hip", "side.hpp", "blocked.hpp", "element.hpp", "symbolic.hip",
+                  "lfem_internal.hpp")
+KERNEL_NAME = "k_side<P2 surface, Q=6, M, A>"
+
+
 def kernel_source_digest() -> str:
+    """Digest of the sources that define the timed kernel and its schedule."""
     h = hashlib.sha256()
-    for f in ("numeric.hip", "element.hpp"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2605_14035_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -41,7 +47,7 @@ def kernel_source_digest() -> str:
 def read_traffic(digest: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_blocked_p2_ellipsoid_655360_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "k_side_p2_ellipsoid_655360_traffic.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -70,6 +76,53 @@ def cpu_baseline(mesh):
                       f"median of 3 runs: {t:.2f} s"}
 
 
+def batched_vs_plain(lf, torch, meshgen, reps=5):
+    """256 displaced geodesic spheres (P1/P2 alternating): M + A of every mesh by
+    one replay of the batched graph vs 256 per-mesh launches on one stream."""
+    meshes = meshgen.config4()
+    dms = [lf.DeviceMesh.from_dict(m) for m in meshes]
+    for d in dms:
+        d.build_pattern()
+    what = lf.LFEM_M | lf.LFEM_A
+    vals = [torch.empty(max(d.nnz, 1), dtype=torch.float64, device="cuda") for d in dms for _ in range(2)]
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for i, d in enumerate(dms):
+            lf.lfem_assemble(d.handle, d.pattern, what, None, None, vals[2 * i], vals[2 * i + 1], None,
+                             lf.LFEM_SCATTER_BLOCKED, stream)
+
+    b = lf.lfem_batch_create([d.handle for d in dms], [d.pattern for d in dms], what, 1)
+
+    def batched():
+        lf.lfem_assemble_batch(b, vals, stream)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return statistics.median(t)
+
+    t_plain = best(plain)   # per-mesh schedules as tuned by the batch
+    t_batch = best(batched)
+    T = sum(d.T for d in dms)
+    res = {"meshes": len(dms), "elements": T, "nnz": sum(d.nnz for d in dms), "matrices": "M+A",
+           "plain_ms": t_plain, "batched_ms": t_batch, "speedup": t_plain / t_batch,
+           "batched_elements_per_s": T / (t_batch * 1e-3)}
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +130,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scatter", default="blocked", choices=["blocked", "staged", "atomic"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a 256 MiB device copy 3 times (a kernel of known traffic that "
+                         "calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); multi-GPU runs are "
@@ -90,6 +147,13 @@ def main():
     import paper_2605_14035_amd as lf
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     mesh = meshgen.config2()
     gen_s = time.perf_counter() - t0
@@ -159,15 +223,19 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_blocked<P2 surface, M, A>", "alg_bytes_per_launch": b_alg,
+            "kernel": KERNEL_NAME, "alg_bytes_per_launch": b_alg,
             "kernel_ms_mean": kern_ms, "kernel_ms_min": min(ev_ms),
             "kernel_source_digest": digest,
         },
         "pattern_build_s": pattern_s,
     }
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(mesh)
     dm.close()
+    if not args.no_batch:
+        print("[bench] batched vs plain (256 meshes)", file=sys.stderr, flush=True)
+        result["batched_vs_plain"] = batched_vs_plain(lf, torch, meshgen)
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(mesh)
     print(json.dumps(result))
 
 

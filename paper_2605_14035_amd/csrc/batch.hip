@@ -34,6 +34,7 @@ struct lfem_batch_s {
     int *counter = nullptr;
     size_t lds = 0;
     int dump = 0;  // first LDS dump entry (= largest block capacity)
+    int rs = 0;    // doubles of one LDS matrix region
     int grid = 0;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
@@ -51,28 +52,28 @@ namespace {
 constexpr int BATCH_NT = kSideThreads;
 
 template <class E, int NM, bool HA>
-__device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *lds, int dump)
+__device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *lds, int dump, int rs)
 {
     constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
     SideBlock<E> s;
     side_load_rec<E>(g, blk, s);
     side_load_first<E>(g, s);
     side_load_coords<E>(g, s);
-    if (g.Q == QA) side_block<E, QA, NM, HA, BATCH_NT>(g, s, lds, dump);
-    else side_block<E, QB, NM, HA, BATCH_NT>(g, s, lds, dump);
+    if (g.Q == QA) side_block<E, QA, NM, HA, BATCH_NT>(g, s, lds, dump, rs);
+    else side_block<E, QB, NM, HA, BATCH_NT>(g, s, lds, dump, rs);
 }
 
-// LDS: value entries up to the largest block capacity of the batch (`dump`
-// entries of NM + HA doubles), then the dump entries
+// LDS: one region of rs doubles per matrix: value entries up to the largest
+// block capacity of the batch (`dump`), then the dump entries
 template <int NM, bool HA>
 __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict__ desc,
                                                     const int2 *__restrict__ items, int n_items,
-                                                    int *__restrict__ counter, int dump)
+                                                    int *__restrict__ counter, int dump, int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
     extern __shared__ double lds[];
     __shared__ int cur;
-    for (int i = threadIdx.x; i < NMAT * dump; i += BATCH_NT) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < NMAT * rs; i += BATCH_NT) lds[i] = 0.0;
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
         __syncthreads();
@@ -82,12 +83,12 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict_
         const int2 w = items[it];
         const BlockArgs g = desc[w.x];
         switch (g.etype) {
-        case S1P1: batch_item<ET<1, 1, 1>, NM, HA>(g, w.y, lds, dump); break;
-        case S1P2: batch_item<ET<1, 1, 2>, NM, HA>(g, w.y, lds, dump); break;
-        case S2P1: batch_item<ET<1, 2, 1>, NM, HA>(g, w.y, lds, dump); break;
-        case S2P2: batch_item<ET<1, 2, 2>, NM, HA>(g, w.y, lds, dump); break;
-        case B2P1: batch_item<ET<0, 2, 1>, NM, HA>(g, w.y, lds, dump); break;
-        case B2P2: batch_item<ET<0, 2, 2>, NM, HA>(g, w.y, lds, dump); break;
+        case S1P1: batch_item<ET<1, 1, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
+        case S1P2: batch_item<ET<1, 1, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
+        case S2P1: batch_item<ET<1, 2, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
+        case S2P2: batch_item<ET<1, 2, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
+        case B2P1: batch_item<ET<0, 2, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
+        case B2P2: batch_item<ET<0, 2, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
         default: break;
         }
     }
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict_
 
 __global__ void k_zero_int(int *p) { *p = 0; }
 
-using BatchKernel = void (*)(const BlockArgs *, const int2 *, int, int *, int);
+using BatchKernel = void (*)(const BlockArgs *, const int2 *, int, int *, int, int);
 
 BatchKernel pick_kernel(unsigned what)
 {
@@ -143,6 +144,7 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     }
     // value entries of the largest block capacity, then the dump entries
     b.dump = max_cap;
+    b.rs = side_region(max_cap, max_row);
     const size_t lds = side_lds_bytes(b.nmat, max_cap, max_row);
     LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "batch block schedule exceeds LDS");
     std::stable_sort(work.begin(), work.end(),
@@ -174,7 +176,7 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     // capture: counter reset (a kernel, not a memset node) + persistent kernel
     LFEM_HIP(hipStreamBeginCapture(b.capture, hipStreamCaptureModeThreadLocal));
     k_zero_int<<<1, 1, 0, b.capture>>>(b.counter);
-    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter, b.dump);
+    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter, b.dump, b.rs);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipStreamEndCapture(b.capture, &g);

@@ -144,11 +144,11 @@ __global__ __launch_bounds__(NT) void k_blocked(const BlockArgs g)
 // tail: its record and element words are loaded right after the current
 // compute, its coordinates before the current write-out.
 template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
-__global__ __launch_bounds__(NT) void k_side(const BlockArgs g)
+__global__ __launch_bounds__(NT) void k_side(const BlockArgs g, int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
     extern __shared__ double lds[];
-    for (int i = threadIdx.x; i < NMAT * g.cap; i += NT) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < NMAT * rs; i += NT) lds[i] = 0.0;
     __syncthreads();
     int vb = blockIdx.x;
     SideBlock<E> s;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(NT) void k_side(const BlockArgs g)
     side_load_first<E>(g, s);
     side_load_coords<E>(g, s);
     for (;;) {
-        const int bad = side_compute<E, Q, NM, HA, NT, MULTI>(g, s, lds, g.cap);
+        const int bad = side_compute<E, Q, NM, HA, NT, MULTI>(g, s, lds, g.cap, rs);
         if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
         const int vn = vb + static_cast<int>(gridDim.x);
         const bool more = vn < g.nb;
@@ -166,10 +166,10 @@ __global__ __launch_bounds__(NT) void k_side(const BlockArgs g)
             side_load_first<E>(g, nxt);
         }
         __syncthreads();
-        side_reduce<E, NMAT, NT>(g, s, lds);
+        side_reduce<E, NMAT, NT>(g, s, lds, rs);
         if (more) side_load_coords<E>(g, nxt);
         __syncthreads();
-        side_write<NMAT, NT>(g, s.base, s.nloc, lds);
+        side_write<NMAT, NT>(g, s.base, s.nloc, lds, rs);
         if (!more) break;
         __syncthreads();
         s = nxt;
@@ -316,7 +316,8 @@ void launch_side_q(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s
     int grid = resident_groups(kp, NT, lds);
     if (grid >= p.sched.nb) grid = p.sched.nb;
     else grid &= ~7;  // keep each workgroup on the XCD its block range belongs to
-    kern<<<std::max(grid, 1), NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]));
+    kern<<<std::max(grid, 1), NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]),
+                                            side_region(p.sched.cap, p.max_row));
     LFEM_HIP(hipGetLastError());
 }
 

@@ -17,14 +17,15 @@
 // contributions is stored in its own side slot and the slots of one entry are
 // summed in element order after a barrier.
 //
-// LDS of one block, entry-major with the NMAT matrices of one entry adjacent
-// (entry e of matrix m at lds[e * NMAT + m]): entries [0, cap) hold the block's
-// values followed by its side slots; `dump` entries from index `dump` on take
-// the contributions to rows outside the block (one per lane and column
-// offset, never read), so the scatter needs no branch.  Value entries are
-// all zero between blocks: the ordered
-// reduction clears the side slots it reads and the write-out clears the
-// values it stores, so no separate clearing pass runs per block.
+// LDS of one block: one region of `rs` doubles per matrix (entry e of matrix
+// m at lds[m * rs + e]); in each region, entries [0, cap) hold the block's
+// values followed by its side slots, and `dump` entries from index `dump` on
+// take the contributions to rows outside the block (one per lane and column
+// offset, never read), so the scatter needs no branch.  (Separate regions
+// spread one matrix's scattered 8-byte adds over all LDS banks.)  Value
+// entries are all zero between blocks: the ordered reduction clears the side
+// slots it reads and the write-out clears the values it stores, so no
+// separate clearing pass runs per block.
 //
 // Memory latency dominates a block's life, so its dependent loads are kept
 // short: one scalar load of the block record (element, row, value and
@@ -210,7 +211,7 @@ __device__ __forceinline__ void side_pairs(const double (&f)[NM > 0 ? NM : 1][Q]
                                            const double (&kq)[HA ? Q : 1][E::nsym],
                                            const double *__restrict__ tabp, const int32_t (&rb)[E::k],
                                            const uint32_t (&ow)[SideLayout<E>::KW],
-                                           const uint32_t (&nw)[E::k], double *lds, int nloc)
+                                           const uint32_t (&nw)[E::k], double *lds, int nloc, int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
     constexpr int PS = Q * (1 + E::nsym);
@@ -251,11 +252,11 @@ __device__ __forceinline__ void side_pairs(const double (&f)[NM > 0 ? NM : 1][Q]
                 ea = sslot != 0xffffu ? nloc + static_cast<int32_t>(sslot) : ea;
             }
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) lds_add(&lds[ea * NMAT + mat], v[mat]);
+            for (int mat = 0; mat < NMAT; ++mat) lds_add(&lds[mat * rs + ea], v[mat]);
             if (a != b) {
                 const int32_t eb = rb[b] + slot_off<E::k>(ow, b, a);
 #pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) lds_add(&lds[eb * NMAT + mat], v[mat]);
+                for (int mat = 0; mat < NMAT; ++mat) lds_add(&lds[mat * rs + eb], v[mat]);
             }
         }
 }
@@ -265,7 +266,7 @@ template <class E, int Q, int NM, bool HA>
 __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const int32_t (&nid)[E::k],
                                             const double (&x)[E::n][E::k],
                                             const uint32_t (&ow)[SideLayout<E>::KW], const uint32_t (&nw)[E::k],
-                                            double *lds, int32_t dump)
+                                            double *lds, int32_t dump, int rs)
 {
     const int32_t mine = dump + static_cast<int32_t>(threadIdx.x & 63);
     int32_t rb[E::k];
@@ -277,7 +278,10 @@ __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const 
     double f[NM > 0 ? NM : 1][Q];
     double kq[HA ? Q : 1][E::nsym];
     const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
-    side_pairs<E, Q, NM, HA>(f, kq, g.tabp, rb, ow, nw, lds, nloc);
+    // keep the pair sums out of the geometry phase (starting them early would
+    // hold every pair's partial sums in registers)
+    __builtin_amdgcn_sched_barrier(0);
+    side_pairs<E, Q, NM, HA>(f, kq, g.tabp, rb, ow, nw, lds, nloc, rs);
     return bad;
 }
 
@@ -286,11 +290,12 @@ __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const 
 // first NT of the list are loaded here, with their own registers; without it
 // the block must hold at most NT elements.
 template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
-__device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump)
+__device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
+                                            int rs)
 {
     const int tid = threadIdx.x;
     int bad = 0;
-    if (s.e0 + tid < s.e1) bad += side_element<E, Q, NM, HA>(g, s.nloc, s.nid, s.x, s.ow, s.nw, lds, dump);
+    if (s.e0 + tid < s.e1) bad += side_element<E, Q, NM, HA>(g, s.nloc, s.nid, s.x, s.ow, s.nw, lds, dump, rs);
     if constexpr (MULTI)
     for (int32_t c0 = s.e0 + NT; c0 < s.e1; c0 += NT) {
         const int32_t idx = c0 + tid;
@@ -300,7 +305,7 @@ __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<
             double x[E::n][E::k];
             side_load_elem<E>(g, idx, nid, ow, nw);
             gather_coords<E>(nid, g.coords, g.N, x);
-            bad += side_element<E, Q, NM, HA>(g, s.nloc, nid, x, ow, nw, lds, dump);
+            bad += side_element<E, Q, NM, HA>(g, s.nloc, nid, x, ow, nw, lds, dump, rs);
         }
     }
     return bad;
@@ -309,50 +314,43 @@ __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<
 // sum ordered diagonal w0 = (entry | count << 16) from its side slots starting
 // at `first`, in element order, clearing the slots
 template <int NMAT>
-__device__ __forceinline__ void side_reduce_one(uint32_t w0, uint32_t first, int nloc, double *lds)
+__device__ __forceinline__ void side_reduce_one(uint32_t w0, uint32_t first, int nloc, double *lds, int rs)
 {
     const uint32_t idx = w0 & 0xffffu, cnt = w0 >> 16;
-    double acc[NMAT];
 #pragma unroll
-    for (int mat = 0; mat < NMAT; ++mat) acc[mat] = 0.0;
-    double *slots = lds + (nloc + first) * NMAT;
-    for (uint32_t j = 0; j < cnt; ++j)
-#pragma unroll
-        for (int mat = 0; mat < NMAT; ++mat) {
-            acc[mat] += slots[j * NMAT + mat];
-            slots[j * NMAT + mat] = 0.0;
+    for (int mat = 0; mat < NMAT; ++mat) {
+        double *reg = lds + mat * rs;
+        double *slots = reg + nloc + first;
+        double acc = 0.0;
+        for (uint32_t j = 0; j < cnt; ++j) {
+            acc += slots[j];
+            slots[j] = 0.0;
         }
-#pragma unroll
-    for (int mat = 0; mat < NMAT; ++mat) lds[idx * NMAT + mat] = acc[mat];
+        reg[idx] = acc;
+    }
 }
 
 template <class E, int NMAT, int NT>
-__device__ __forceinline__ void side_reduce(const BlockArgs &g, const SideBlock<E> &s, double *lds)
+__device__ __forceinline__ void side_reduce(const BlockArgs &g, const SideBlock<E> &s, double *lds, int rs)
 {
     const int32_t tid = threadIdx.x;
-    if (s.o0 + tid < s.o1) side_reduce_one<NMAT>(s.ord0, s.ord1, s.nloc, lds);
+    if (s.o0 + tid < s.o1) side_reduce_one<NMAT>(s.ord0, s.ord1, s.nloc, lds, rs);
     for (int32_t r = s.o0 + tid + NT; r < s.o1; r += NT)
         side_reduce_one<NMAT>(g.bord[2 * static_cast<int64_t>(r)], g.bord[2 * static_cast<int64_t>(r) + 1],
-                              s.nloc, lds);
+                              s.nloc, lds, rs);
 }
 
 // store the block's values and clear them in LDS
 template <int NMAT, int NT>
-__device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nloc, double *lds)
+__device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nloc, double *lds, int rs)
 {
-    for (int i = threadIdx.x; i < nloc; i += NT) {
-        double *e = lds + i * NMAT;
-        if constexpr (NMAT == 2) {
-            const double2 v = *reinterpret_cast<const double2 *>(e);
-            g.v[0][base + i] = v.x;
-            g.v[1][base + i] = v.y;
-            *reinterpret_cast<double2 *>(e) = make_double2(0.0, 0.0);
-        } else {
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) {
-                g.v[mat][base + i] = e[mat];
-                e[mat] = 0.0;
-            }
+    for (int mat = 0; mat < NMAT; ++mat) {
+        double *__restrict__ out = g.v[mat] + base;
+        double *reg = lds + mat * rs;
+        for (int i = threadIdx.x; i < nloc; i += NT) {
+            out[i] = reg[i];
+            reg[i] = 0.0;
         }
     }
 }
@@ -361,26 +359,30 @@ __device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nlo
 // flight) in s.  LDS value entries must be all zero on entry (and no thread
 // may still be writing out a previous block) and are all zero on return.
 template <class E, int Q, int NM, bool HA, int NT>
-__device__ __forceinline__ void side_block(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump)
+__device__ __forceinline__ void side_block(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
+                                           int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
-    const int bad = side_compute<E, Q, NM, HA, NT, true>(g, s, lds, dump);
+    const int bad = side_compute<E, Q, NM, HA, NT, true>(g, s, lds, dump, rs);
     if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
     __syncthreads();
-    side_reduce<E, NMAT, NT>(g, s, lds);
+    side_reduce<E, NMAT, NT>(g, s, lds, rs);
     __syncthreads();
-    side_write<NMAT, NT>(g, s.base, s.nloc, lds);
+    side_write<NMAT, NT>(g, s.base, s.nloc, lds, rs);
     __syncthreads();
 }
 
 // dump entries after the value entries: one per lane and column offset
 inline int side_dump_entries(int max_row) { return 64 + max_row; }
 
+// doubles of one matrix region
+inline int side_region(int cap, int max_row) { return cap + side_dump_entries(max_row); }
+
 // bytes of dynamic LDS of the side-slot kernels for NMAT matrices, value
 // capacity cap and longest row max_row
 inline size_t side_lds_bytes(int nmat, int cap, int max_row)
 {
-    return static_cast<size_t>(nmat) * (cap + side_dump_entries(max_row)) * sizeof(double);
+    return static_cast<size_t>(nmat) * side_region(cap, max_row) * sizeof(double);
 }
 
 }  // namespace lfem
