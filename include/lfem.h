@@ -70,7 +70,8 @@ typedef int lfem_status;
 
 /* numeric scatter variants (how local matrices are summed into CSR values) */
 #define LFEM_SCATTER_AUTO 0     /* the pattern's tuned choice (blocked unless tuned otherwise) */
-#define LFEM_SCATTER_BLOCKED 1  /* deterministic: row blocks accumulated in LDS, colour order */
+#define LFEM_SCATTER_BLOCKED 1  /* deterministic: row blocks accumulated in LDS (order-free adds
+                                   where at most two contributions meet, fixed order elsewhere) */
 #define LFEM_SCATTER_STAGED 2   /* deterministic: local matrices staged, slot-sorted segmented sum */
 #define LFEM_SCATTER_ATOMIC 3   /* FP64 atomics into zeroed values; summation order not fixed */
 
@@ -168,9 +169,10 @@ lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what
                                   int *variant_out);
 
 /*
- * Batched assembly: many meshes (any element types, uneven sizes) assembled
- * in one persistent launch replayed from a HIP graph.  what: matrices per
- * mesh (LFEM_M | LFEM_A; coefficients are not supported in batches).
+ * Batched assembly: many meshes (curves, surfaces and planar domains of any
+ * order and rule, uneven sizes) assembled in one persistent launch replayed
+ * from a HIP graph.  what: matrices per mesh (LFEM_M | LFEM_A; coefficients
+ * are not supported in batches).  Tetrahedral meshes: LFEM_EUNSUPPORTED.
  * autotune != 0 times the candidate launch shapes once at creation
  * (SYNCHRONISES stream).  The handle keeps the mesh and pattern handles
  * (which must outlive it).
