@@ -16,8 +16,10 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 const char *last_error() { return g_last_error.c_str(); }
 
-// defaults of the blocked scatter's schedule
-constexpr int kDefaultCap = 4096;
+// defaults of the blocked scatter's schedule: values per block and matrix
+// (with two matrices, M + A, two workgroups still fit in one CU's 160 KB of
+// LDS) and rows per block
+constexpr int kDefaultCap = 4864;
 constexpr int kMaxRows = kBlockMaxRows;
 
 }  // namespace lfem

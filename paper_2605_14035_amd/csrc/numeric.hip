@@ -26,6 +26,7 @@
 
 #include <map>
 #include <tuple>
+#include <type_traits>
 
 #include "side.hpp"
 
@@ -34,70 +35,101 @@ namespace lfem {
 namespace {
 
 // ---------------------------------------------------------------------------
-// atomic variant
+// atomic variant: one thread per element, values added to the global CSR
+// values with FP64 atomics (formed pair by pair, or accumulated point by point
+// for tetrahedra)
 // ---------------------------------------------------------------------------
-template <class E, int NM, bool HA>
-__global__ __launch_bounds__(256) void k_atomic(
-    const double *__restrict__ coords, const int32_t *__restrict__ conn,
-    const double *__restrict__ tab, int64_t N, int64_t T, int Q, const double *__restrict__ cm0,
-    const double *__restrict__ cm1, const double *__restrict__ ca,
-    const int32_t *__restrict__ row_ptr, const uint8_t *__restrict__ off8, int kkp,
-    double *__restrict__ v0, double *__restrict__ v1, double *__restrict__ v2,
-    unsigned long long *__restrict__ degenerate)
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                                const int32_t *__restrict__ row_ptr,
+                                                const uint8_t *__restrict__ off8, int kkp)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= T) return;
+    constexpr int NMAT = NM + (HA ? 1 : 0);
     int32_t nid[E::k];
 #pragma unroll
     for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
     double x[E::n][E::k];
-    gather_coords<E>(nid, coords, N, x);
-    double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
-    const int bad = element_local<E, NM, HA>(nid, x, tab, Q, cm0, cm1, ca, LM, LA);
-    if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));
-    constexpr int NMAT = NM + (HA ? 1 : 0);
-    double *outs[3] = {v0, v1, v2};
+    gather_coords<E>(nid, g.coords, g.N, x);
     const uint8_t *o = off8 + e * kkp;
+    if constexpr (E::d == 3) {
+        // tetrahedra: accumulate the local matrices point by point (see k_stage)
+        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
+        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
 #pragma unroll
-    for (int a = 0; a < E::k; ++a) {
-        const int32_t rb = row_ptr[nid[a]];
+        for (int a = 0; a < E::k; ++a) {
+            const int32_t rb = row_ptr[nid[a]];
 #pragma unroll
-        for (int b = 0; b < E::k; ++b) {
-            const int32_t slot = rb + o[a * E::k + b];
+            for (int b = 0; b < E::k; ++b)
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat)
-                unsafeAtomicAdd(outs[mat] + slot, local_value<E, NM, HA>(mat, a, b, LM, LA));
+                for (int mat = 0; mat < NMAT; ++mat)
+                    unsafeAtomicAdd(g.v[mat] + rb + o[a * E::k + b], local_value<E, NM, HA>(mat, a, b, LM, LA));
         }
+        return;
     }
+    double f[NM > 0 ? NM : 1][Q];
+    double kq[HA ? Q : 1][E::nsym];
+    const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
+    if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+    int p = 0;
+#pragma unroll
+    for (int a = 0; a < E::k; ++a)
+#pragma unroll
+        for (int b = a; b < E::k; ++b, ++p) {
+            double v[NMAT];
+            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
+            const int32_t sa = row_ptr[nid[a]] + o[a * E::k + b];
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sa, v[mat]);
+            if (a != b) {
+                const int32_t sb = row_ptr[nid[b]] + o[b * E::k + a];
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sb, v[mat]);
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
-// staged variant
+// staged variant: one thread per element writes its local values, structure
+// of arrays stage[(mat * np + p) * T + e]
 // ---------------------------------------------------------------------------
-template <class E, int NM, bool HA>
-__global__ __launch_bounds__(256) void k_stage(
-    const double *__restrict__ coords, const int32_t *__restrict__ conn,
-    const double *__restrict__ tab, int64_t N, int64_t T, int Q, const double *__restrict__ cm0,
-    const double *__restrict__ cm1, const double *__restrict__ ca, double *__restrict__ stage,
-    unsigned long long *__restrict__ degenerate)
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                               double *__restrict__ stage)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= T) return;
+    constexpr int NMAT = NM + (HA ? 1 : 0);
     int32_t nid[E::k];
 #pragma unroll
     for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
     double x[E::n][E::k];
-    gather_coords<E>(nid, coords, N, x);
-    double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
-    const int bad = element_local<E, NM, HA>(nid, x, tab, Q, cm0, cm1, ca, LM, LA);
-    if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));
+    gather_coords<E>(nid, g.coords, g.N, x);
+    if constexpr (E::d == 3) {
+        // tetrahedra: the Q-point data of 11 points (77 doubles) outweighs the
+        // local matrices, so accumulate those point by point instead
+        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
+        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
 #pragma unroll
-    for (int s = 0; s < NM; ++s)
+        for (int p = 0; p < E::np; ++p)
 #pragma unroll
-        for (int p = 0; p < E::np; ++p) stage[(s * E::np + p) * T + e] = LM[s][p];
-    if constexpr (HA) {
+            for (int mat = 0; mat < NMAT; ++mat)
+                stage[(mat * E::np + p) * T + e] = mat < NM ? LM[mat][p] : LA[p];
+    } else {
+        double f[NM > 0 ? NM : 1][Q];
+        double kq[HA ? Q : 1][E::nsym];
+        const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
 #pragma unroll
-        for (int p = 0; p < E::np; ++p) stage[(NM * E::np + p) * T + e] = LA[p];
+        for (int p = 0; p < E::np; ++p) {
+            double v[NMAT];
+            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat) stage[(mat * E::np + p) * T + e] = v[mat];
+        }
     }
 }
 
@@ -213,6 +245,18 @@ Outs arrange(const NumericOut &o)
     return r;
 }
 
+// the two rules of each element dimension (points: segment 2, 3; triangle
+// 3, 6; tetrahedron 4, 11) as compile-time constants
+template <class E, class F>
+void with_rule(int Q, F &&fn)
+{
+    constexpr int QA = E::d == 1 ? 2 : (E::d == 2 ? 3 : 4);
+    constexpr int QB = E::d == 1 ? 3 : (E::d == 2 ? 6 : 11);
+    if (Q == QA) return fn(std::integral_constant<int, QA>{});
+    if (Q == QB) return fn(std::integral_constant<int, QB>{});
+    throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
+}
+
 template <class E, int NM, bool HA, int NT>
 void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
 template <class E, int NM, bool HA, int NT>
@@ -232,9 +276,11 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
     if (variant == LFEM_SCATTER_ATOMIC) {
         for (int mat = 0; mat < NMAT; ++mat)
             k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
-        k_atomic<E, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(
-            m.coords, m.conn, m.tab, m.N, m.T, m.Q, o.cm0, o.cm1, o.ca, p.row_ptr, p.off8, p.kkp,
-            o.v[0], o.v[1], o.v[2], m.degenerate);
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_atomic<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.row_ptr,
+                                                                                       p.off8, p.kkp);
+        });
         LFEM_HIP(hipGetLastError());
         return;
     }
@@ -248,8 +294,10 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
             p.stage_bytes = need;
         }
-        k_stage<E, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(
-            m.coords, m.conn, m.tab, m.N, m.T, m.Q, o.cm0, o.cm1, o.ca, p.stage, m.degenerate);
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_stage<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.stage);
+        });
         LFEM_HIP(hipGetLastError());
         k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, m.T, p.cptr, p.clist,
                                                                    p.stage, o.v[0], o.v[1], o.v[2]);
@@ -324,20 +372,14 @@ void launch_side_q(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s
 template <class E, int NM, bool HA, int NT>
 void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
 {
-    // the two rules of each dimension (segment 2, 3; triangle 3, 6 points)
-    constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
     // blocks of more than NT elements (P1 meshes) need the chunk loop
-    const bool multi = p.sched.max_elems > NT;
-    if constexpr (E::p == 1) {
-        if (m.Q == QA) return launch_side_q<E, QA, NM, HA, NT, true>(m, p, o, lds, s);
-        if (m.Q == QB) return launch_side_q<E, QB, NM, HA, NT, true>(m, p, o, lds, s);
-    } else {
-        if (m.Q == QA) return multi ? launch_side_q<E, QA, NM, HA, NT, true>(m, p, o, lds, s)
-                                    : launch_side_q<E, QA, NM, HA, NT, false>(m, p, o, lds, s);
-        if (m.Q == QB) return multi ? launch_side_q<E, QB, NM, HA, NT, true>(m, p, o, lds, s)
-                                    : launch_side_q<E, QB, NM, HA, NT, false>(m, p, o, lds, s);
-    }
-    throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
+    const bool multi = E::p == 1 || p.sched.max_elems > NT;
+    with_rule<E>(m.Q, [&](auto qc) {
+        constexpr int Q = decltype(qc)::value;
+        if constexpr (E::p == 1) launch_side_q<E, Q, NM, HA, NT, true>(m, p, o, lds, s);
+        else if (multi) launch_side_q<E, Q, NM, HA, NT, true>(m, p, o, lds, s);
+        else launch_side_q<E, Q, NM, HA, NT, false>(m, p, o, lds, s);
+    });
 }
 
 template <class E>

@@ -200,12 +200,48 @@ __device__ __forceinline__ int32_t slot_off(const uint32_t (&ow)[KW], int a, int
     return static_cast<int32_t>((ow[slot >> 2] >> (8 * (slot & 3))) & 0xffu);
 }
 
+// values of local pair p (a <= b) of every selected matrix from the Q-point
+// data and the pair-major reference tensors.  Sums are split into
+// independent chains (mass: by point parity; stiffness: by slot of K) to
+// shorten the dependent FMA sequences.
+template <class E, int Q, int NM, bool HA>
+__device__ __forceinline__ void pair_values(int p, const double (&f)[NM > 0 ? NM : 1][Q],
+                                            const double (&kq)[HA ? Q : 1][E::nsym],
+                                            const double *__restrict__ tabp,
+                                            double (&v)[NM + (HA ? 1 : 0)])
+{
+    constexpr int PS = Q * (1 + E::nsym);
+    constexpr int CA = E::nsym > 1 ? E::nsym : 3;  // stiffness chains
+    cdouble *t = const_table(tabp) + p * PS;
+#pragma unroll
+    for (int s = 0; s < NM; ++s) {
+        double acc[2] = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q & 1] = fma(f[s][q], t[q], acc[q & 1]);
+        v[s] = acc[0] + acc[1];
+    }
+    if constexpr (HA) {
+        double acc[CA];
+#pragma unroll
+        for (int c = 0; c < CA; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int si = 0; si < E::nsym; ++si) {
+                const int c = (q * E::nsym + si) % CA;
+                acc[c] = fma(kq[q][si], t[Q + q * E::nsym + si], acc[c]);
+            }
+        double sum = acc[0];
+#pragma unroll
+        for (int c = 1; c < CA; ++c) sum += acc[c];
+        v[NM] = sum;
+    }
+}
+
 // form the element's values pair by pair and add them to the block in LDS.
 // rb[a] is the entry of node a's row start in the block, or the lane's dump
 // entry if the row is outside the block; nw[a] >> 16 is the side slot of the
-// contribution (a, a) (0xffff: none).  Sums are split into independent
-// chains (mass: by point parity; stiffness: by slot of K) to shorten the
-// dependent FMA sequences.
+// contribution (a, a) (0xffff: none).
 template <class E, int Q, int NM, bool HA>
 __device__ __forceinline__ void side_pairs(const double (&f)[NM > 0 ? NM : 1][Q],
                                            const double (&kq)[HA ? Q : 1][E::nsym],
@@ -214,38 +250,13 @@ __device__ __forceinline__ void side_pairs(const double (&f)[NM > 0 ? NM : 1][Q]
                                            const uint32_t (&nw)[E::k], double *lds, int nloc, int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
-    constexpr int PS = Q * (1 + E::nsym);
-    constexpr int CA = E::nsym > 1 ? E::nsym : 3;  // stiffness chains
     int p = 0;
 #pragma unroll
     for (int a = 0; a < E::k; ++a)
 #pragma unroll
         for (int b = a; b < E::k; ++b, ++p) {
-            cdouble *t = const_table(tabp) + p * PS;
             double v[NMAT];
-#pragma unroll
-            for (int s = 0; s < NM; ++s) {
-                double acc[2] = {0.0, 0.0};
-#pragma unroll
-                for (int q = 0; q < Q; ++q) acc[q & 1] = fma(f[s][q], t[q], acc[q & 1]);
-                v[s] = acc[0] + acc[1];
-            }
-            if constexpr (HA) {
-                double acc[CA];
-#pragma unroll
-                for (int c = 0; c < CA; ++c) acc[c] = 0.0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q)
-#pragma unroll
-                    for (int si = 0; si < E::nsym; ++si) {
-                        const int c = (q * E::nsym + si) % CA;
-                        acc[c] = fma(kq[q][si], t[Q + q * E::nsym + si], acc[c]);
-                    }
-                double sum = acc[0];
-#pragma unroll
-                for (int c = 1; c < CA; ++c) sum += acc[c];
-                v[NM] = sum;
-            }
+            pair_values<E, Q, NM, HA>(p, f, kq, tabp, v);
             int32_t ea = rb[a] + slot_off<E::k>(ow, a, b);
             if (a == b) {
                 const uint32_t sslot = nw[a] >> 16;

@@ -53,7 +53,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
     const char *env = std::getenv("LFEM_TUNE_VERBOSE");
     const bool verbose = env && env[0] == '1';
     try {
-        const int caps[] = {1024, 2048, 3072, 4096, 5120, 6144};
+        const int caps[] = {2048, 3072, 4096, 4864, 6144, 8192};
         for (int cap : caps) {
             if (cap < p.max_row) continue;
             if (static_cast<size_t>(nmat) * cap * 8 + 4 * 1025 > 160 * 1024) continue;
