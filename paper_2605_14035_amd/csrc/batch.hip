@@ -59,8 +59,8 @@ __device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *
     side_load_rec<E>(g, blk, s);
     side_load_first<E>(g, s);
     side_load_coords<E>(g, s);
-    if (g.Q == QA) side_block<E, QA, NM, HA, BATCH_NT>(g, s, lds, dump, rs);
-    else side_block<E, QB, NM, HA, BATCH_NT>(g, s, lds, dump, rs);
+    if (g.Q == QA) side_block<E, QA, NM, HA, 0, BATCH_NT>(g, s, lds, dump, rs);
+    else side_block<E, QB, NM, HA, 0, BATCH_NT>(g, s, lds, dump, rs);
 }
 
 // LDS: one region of rs doubles per matrix: value entries up to the largest

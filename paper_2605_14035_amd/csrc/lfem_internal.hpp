@@ -179,6 +179,11 @@ struct NumericOut {
     double *vals_m = nullptr, *vals_a = nullptr, *vals_mc = nullptr;
 };
 void launch_numeric(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+// per element family (numeric_<family>.hip)
+void numeric_curve(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+void numeric_surface(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+void numeric_planar(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+void numeric_tet(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
 void fill_zero(double *x, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------

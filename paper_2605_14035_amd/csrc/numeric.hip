@@ -22,399 +22,37 @@
 //             (curves, surfaces, planar meshes, where only diagonals have
 //             more), or colour by colour (tetrahedra; elements of one colour
 //             share no node).
-#include <cmath>
-
-#include <map>
-#include <tuple>
-#include <type_traits>
-
-#include "side.hpp"
+#include "lfem_internal.hpp"
 
 namespace lfem {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// atomic variant: one thread per element, values added to the global CSR
-// values with FP64 atomics (formed pair by pair, or accumulated point by point
-// for tetrahedra)
-// ---------------------------------------------------------------------------
-template <class E, int Q, int NM, bool HA>
-__global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                                const int32_t *__restrict__ row_ptr,
-                                                const uint8_t *__restrict__ off8, int kkp)
-{
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= T) return;
-    constexpr int NMAT = NM + (HA ? 1 : 0);
-    int32_t nid[E::k];
-#pragma unroll
-    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
-    double x[E::n][E::k];
-    gather_coords<E>(nid, g.coords, g.N, x);
-    const uint8_t *o = off8 + e * kkp;
-    if constexpr (E::d == 3) {
-        // tetrahedra: accumulate the local matrices point by point (see k_stage)
-        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
-        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
-        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
-#pragma unroll
-        for (int a = 0; a < E::k; ++a) {
-            const int32_t rb = row_ptr[nid[a]];
-#pragma unroll
-            for (int b = 0; b < E::k; ++b)
-#pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat)
-                    unsafeAtomicAdd(g.v[mat] + rb + o[a * E::k + b], local_value<E, NM, HA>(mat, a, b, LM, LA));
-        }
-        return;
-    }
-    double f[NM > 0 ? NM : 1][Q];
-    double kq[HA ? Q : 1][E::nsym];
-    const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
-    if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
-    int p = 0;
-#pragma unroll
-    for (int a = 0; a < E::k; ++a)
-#pragma unroll
-        for (int b = a; b < E::k; ++b, ++p) {
-            double v[NMAT];
-            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
-            const int32_t sa = row_ptr[nid[a]] + o[a * E::k + b];
-#pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sa, v[mat]);
-            if (a != b) {
-                const int32_t sb = row_ptr[nid[b]] + o[b * E::k + a];
-#pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sb, v[mat]);
-            }
-        }
-}
-
-// ---------------------------------------------------------------------------
-// staged variant: one thread per element writes its local values, structure
-// of arrays stage[(mat * np + p) * T + e]
-// ---------------------------------------------------------------------------
-template <class E, int Q, int NM, bool HA>
-__global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                               double *__restrict__ stage)
-{
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= T) return;
-    constexpr int NMAT = NM + (HA ? 1 : 0);
-    int32_t nid[E::k];
-#pragma unroll
-    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
-    double x[E::n][E::k];
-    gather_coords<E>(nid, g.coords, g.N, x);
-    if constexpr (E::d == 3) {
-        // tetrahedra: the Q-point data of 11 points (77 doubles) outweighs the
-        // local matrices, so accumulate those point by point instead
-        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
-        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
-        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
-#pragma unroll
-        for (int p = 0; p < E::np; ++p)
-#pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat)
-                stage[(mat * E::np + p) * T + e] = mat < NM ? LM[mat][p] : LA[p];
-    } else {
-        double f[NM > 0 ? NM : 1][Q];
-        double kq[HA ? Q : 1][E::nsym];
-        const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
-        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
-#pragma unroll
-        for (int p = 0; p < E::np; ++p) {
-            double v[NMAT];
-            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
-#pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) stage[(mat * E::np + p) * T + e] = v[mat];
-        }
-    }
-}
-
-template <int K, int NMAT>
-__global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
-                                                const int32_t *__restrict__ cptr,
-                                                const int32_t *__restrict__ clist,
-                                                const double *__restrict__ stage,
-                                                double *__restrict__ v0, double *__restrict__ v1,
-                                                double *__restrict__ v2)
-{
-    constexpr int NP = K * (K + 1) / 2;
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= nnz) return;
-    double acc[NMAT];
-#pragma unroll
-    for (int mat = 0; mat < NMAT; ++mat) acc[mat] = 0.0;
-    const int32_t b = cptr[s], end = cptr[s + 1];
-    for (int32_t c = b; c < end; ++c) {
-        const int32_t code = clist[c];
-        const int64_t e = code >> 7;
-        const int ab = code & 127;
-        const int a = ab / K, bb = ab - a * K;
-        const int p = pair_index<K>(a, bb);
-#pragma unroll
-        for (int mat = 0; mat < NMAT; ++mat) acc[mat] += stage[(mat * NP + p) * T + e];
-    }
-    double *outs[3] = {v0, v1, v2};
-#pragma unroll
-    for (int mat = 0; mat < NMAT; ++mat) outs[mat][s] = acc[mat];
-}
-
-template <class E, int NM, bool HA, int NT>
-__global__ __launch_bounds__(NT) void k_blocked(const BlockArgs g)
-{
-    extern __shared__ double lds[];
-    blocked_block<E, NM, HA, NT>(g, xcd_block(blockIdx.x, g.nb), lds);
-}
-
-// Persistent side-slot kernel: workgroup w handles the blocks whose launch
-// order index is w, w + G, w + 2G, ... (G = gridDim.x, a multiple of 8 when
-// smaller than the block count, so every block of one workgroup lies in the
-// range of its XCD).  The next block's loads overlap the current block's
-// tail: its record and element words are loaded right after the current
-// compute, its coordinates before the current write-out.
-template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
-__global__ __launch_bounds__(NT) void k_side(const BlockArgs g, int rs)
-{
-    constexpr int NMAT = NM + (HA ? 1 : 0);
-    extern __shared__ double lds[];
-    for (int i = threadIdx.x; i < NMAT * rs; i += NT) lds[i] = 0.0;
-    __syncthreads();
-    int vb = blockIdx.x;
-    SideBlock<E> s;
-    side_load_rec<E>(g, xcd_block(vb, g.nb), s);
-    side_load_first<E>(g, s);
-    side_load_coords<E>(g, s);
-    for (;;) {
-        const int bad = side_compute<E, Q, NM, HA, NT, MULTI>(g, s, lds, g.cap, rs);
-        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
-        const int vn = vb + static_cast<int>(gridDim.x);
-        const bool more = vn < g.nb;
-        SideBlock<E> nxt;
-        if (more) {
-            side_load_rec<E>(g, xcd_block(vn, g.nb), nxt);
-            side_load_first<E>(g, nxt);
-        }
-        __syncthreads();
-        side_reduce<E, NMAT, NT>(g, s, lds, rs);
-        if (more) side_load_coords<E>(g, nxt);
-        __syncthreads();
-        side_write<NMAT, NT>(g, s.base, s.nloc, lds, rs);
-        if (!more) break;
-        __syncthreads();
-        s = nxt;
-        vb = vn;
-    }
-}
-
-__global__ void k_fill_zero(double *__restrict__ x, int64_t n)
+__global__ void k_zero(double *__restrict__ x, int64_t n)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0.0;
-}
-
-inline unsigned grid_for(int64_t n, int nt) { return static_cast<unsigned>((n + nt - 1) / nt); }
-
-struct Outs {
-    const double *cm0 = nullptr, *cm1 = nullptr, *ca = nullptr;
-    double *v[3] = {nullptr, nullptr, nullptr};
-    int nm = 0;
-    bool ha = false;
-};
-
-Outs arrange(const NumericOut &o)
-{
-    Outs r;
-    if (o.what & LFEM_M) {
-        r.v[r.nm] = o.vals_m;
-        if (r.nm == 0) r.cm0 = nullptr; else r.cm1 = nullptr;
-        ++r.nm;
-    }
-    if (o.what & LFEM_MC) {
-        r.v[r.nm] = o.vals_mc;
-        if (r.nm == 0) r.cm0 = o.coef_c; else r.cm1 = o.coef_c;
-        ++r.nm;
-    }
-    if (o.what & LFEM_A) {
-        r.ha = true;
-        r.v[r.nm] = o.vals_a;
-        r.ca = o.coef_a;
-    }
-    return r;
-}
-
-// the two rules of each element dimension (points: segment 2, 3; triangle
-// 3, 6; tetrahedron 4, 11) as compile-time constants
-template <class E, class F>
-void with_rule(int Q, F &&fn)
-{
-    constexpr int QA = E::d == 1 ? 2 : (E::d == 2 ? 3 : 4);
-    constexpr int QB = E::d == 1 ? 3 : (E::d == 2 ? 6 : 11);
-    if (Q == QA) return fn(std::integral_constant<int, QA>{});
-    if (Q == QB) return fn(std::integral_constant<int, QB>{});
-    throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
-}
-
-template <class E, int NM, bool HA, int NT>
-void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
-template <class E, int NM, bool HA, int NT>
-void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
-
-template <class E, int NM, bool HA>
-void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
-{
-    constexpr int NMAT = NM + (HA ? 1 : 0);
-    if (m.T == 0 || p.nnz == 0) {
-        for (int mat = 0; mat < NMAT; ++mat)
-            if (p.nnz > 0) {
-                k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
-            }
-        return;
-    }
-    if (variant == LFEM_SCATTER_ATOMIC) {
-        for (int mat = 0; mat < NMAT; ++mat)
-            k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
-        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
-        with_rule<E>(m.Q, [&](auto qc) {
-            k_atomic<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.row_ptr,
-                                                                                       p.off8, p.kkp);
-        });
-        LFEM_HIP(hipGetLastError());
-        return;
-    }
-    if (variant == LFEM_SCATTER_STAGED) {
-        build_staged(m, p, s);
-        const size_t need = static_cast<size_t>(NMAT) * E::np * m.T * sizeof(double);
-        if (p.stage_bytes < need) {
-            dev_free(p.stage);
-            p.stage = nullptr;
-            p.stage_bytes = 0;
-            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
-            p.stage_bytes = need;
-        }
-        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
-        with_rule<E>(m.Q, [&](auto qc) {
-            k_stage<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.stage);
-        });
-        LFEM_HIP(hipGetLastError());
-        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, m.T, p.cptr, p.clist,
-                                                                   p.stage, o.v[0], o.v[1], o.v[2]);
-        LFEM_HIP(hipGetLastError());
-        return;
-    }
-    // blocked
-    LFEM_REQUIRE(p.sched.nb > 0, LFEM_EUNSUPPORTED, "pattern has no block schedule");
-    constexpr int NT = kSideThreads;
-    const bool side = p.sched.side_mode;
-    const size_t lds = side ? side_lds_bytes(NMAT, p.sched.cap, p.max_row) : block_lds_bytes(p, NMAT);
-    LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "block schedule exceeds LDS");
-    if (side) {
-        if constexpr (E::d <= 2) return launch_side<E, NM, HA, NT>(m, p, o, lds, s);
-        throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
-    }
-    return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
-}
-
-// allow more than 64 KB of dynamic LDS for kern (once per size increase)
-void allow_lds(const void *kern, size_t lds)
-{
-    static thread_local std::map<const void *, size_t> granted;
-    size_t &g = granted[kern];
-    if (lds > 64 * 1024 && lds > g) {
-        LFEM_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        g = lds;
-    }
-}
-
-// workgroups of kern that are resident on the device at once
-int resident_groups(const void *kern, int nt, size_t lds)
-{
-    static thread_local std::map<std::tuple<const void *, size_t, int>, int> known;
-    int dev = 0;
-    LFEM_HIP(hipGetDevice(&dev));
-    const auto key = std::make_tuple(kern, lds, dev);
-    auto it = known.find(key);
-    if (it != known.end()) return it->second;
-    int per_cu = 0, cus = 0;
-    LFEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
-    LFEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    LFEM_REQUIRE(per_cu > 0, LFEM_EUNSUPPORTED, "block kernel does not fit on a compute unit");
-    const int r = per_cu * cus;
-    known.emplace(key, r);
-    return r;
-}
-
-template <class E, int NM, bool HA, int NT>
-void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
-{
-    auto kern = k_blocked<E, NM, HA, NT>;
-    allow_lds(reinterpret_cast<const void *>(kern), lds);
-    kern<<<p.sched.nb, NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]));
-    LFEM_HIP(hipGetLastError());
-}
-
-template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
-void launch_side_q(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
-{
-    auto kern = k_side<E, Q, NM, HA, NT, MULTI>;
-    const void *kp = reinterpret_cast<const void *>(kern);
-    allow_lds(kp, lds);
-    int grid = resident_groups(kp, NT, lds);
-    if (grid >= p.sched.nb) grid = p.sched.nb;
-    else grid &= ~7;  // keep each workgroup on the XCD its block range belongs to
-    kern<<<std::max(grid, 1), NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]),
-                                            side_region(p.sched.cap, p.max_row));
-    LFEM_HIP(hipGetLastError());
-}
-
-template <class E, int NM, bool HA, int NT>
-void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
-{
-    // blocks of more than NT elements (P1 meshes) need the chunk loop
-    const bool multi = E::p == 1 || p.sched.max_elems > NT;
-    with_rule<E>(m.Q, [&](auto qc) {
-        constexpr int Q = decltype(qc)::value;
-        if constexpr (E::p == 1) launch_side_q<E, Q, NM, HA, NT, true>(m, p, o, lds, s);
-        else if (multi) launch_side_q<E, Q, NM, HA, NT, true>(m, p, o, lds, s);
-        else launch_side_q<E, Q, NM, HA, NT, false>(m, p, o, lds, s);
-    });
-}
-
-template <class E>
-void run_type(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
-{
-    switch (o.nm * 2 + (o.ha ? 1 : 0)) {
-    case 1: run<E, 0, true>(m, p, o, variant, s); break;
-    case 2: run<E, 1, false>(m, p, o, variant, s); break;
-    case 3: run<E, 1, true>(m, p, o, variant, s); break;
-    case 4: run<E, 2, false>(m, p, o, variant, s); break;
-    case 5: run<E, 2, true>(m, p, o, variant, s); break;
-    default: throw Error{LFEM_EINVAL, "no matrix selected"};
-    }
 }
 
 }  // namespace
 
 void fill_zero(double *x, int64_t n, hipStream_t s)
 {
-    if (n > 0) k_fill_zero<<<grid_for(n, 256), 256, 0, s>>>(x, n);
+    if (n > 0) k_zero<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(x, n);
     LFEM_HIP(hipGetLastError());
 }
 
 void launch_numeric(Mesh &m, Pattern &p, const NumericOut &no, int variant, hipStream_t s)
 {
-    const Outs o = arrange(no);
     switch (m.etype) {
-    case S1P1: run_type<ET<1, 1, 1>>(m, p, o, variant, s); break;
-    case S1P2: run_type<ET<1, 1, 2>>(m, p, o, variant, s); break;
-    case S2P1: run_type<ET<1, 2, 1>>(m, p, o, variant, s); break;
-    case S2P2: run_type<ET<1, 2, 2>>(m, p, o, variant, s); break;
-    case B2P1: run_type<ET<0, 2, 1>>(m, p, o, variant, s); break;
-    case B2P2: run_type<ET<0, 2, 2>>(m, p, o, variant, s); break;
-    case B3P1: run_type<ET<0, 3, 1>>(m, p, o, variant, s); break;
-    case B3P2: run_type<ET<0, 3, 2>>(m, p, o, variant, s); break;
+    case S1P1:
+    case S1P2: numeric_curve(m, p, no, variant, s); break;
+    case S2P1:
+    case S2P2: numeric_surface(m, p, no, variant, s); break;
+    case B2P1:
+    case B2P2: numeric_planar(m, p, no, variant, s); break;
+    case B3P1:
+    case B3P2: numeric_tet(m, p, no, variant, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
     }
 }

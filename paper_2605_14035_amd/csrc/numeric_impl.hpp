@@ -1,0 +1,456 @@
+// Kernels and launchers of the numeric phase, instantiated per element family
+// by numeric_curve.hip, numeric_surface.hip, numeric_planar.hip and
+// numeric_tet.hip.
+//
+// Per element and quadrature point (section 3.2 and Listing 1 (c)-(e)):
+//   J = DF = sum_a x_a (grad_hat phi_a)^T              (n x d)
+//   G = J^T J,  mu = sqrt(det G)  (curve / surface: |t| or |t1 x t2|),
+//               mu = |det J|       (bulk)
+//   K = G^{-1}: the tangential gradient of phi_a is J K g_a, so
+//   grad phi_a . grad phi_b = g_a^T K g_b  (equal to the paper's C^T [g;0]
+//   with C = L^{-1}, L = [J, normal]; no normal vector is needed)
+//   M_loc[a][b] += w mu c_h phi_a phi_b,  A_loc[a][b] += w mu a_h g_a^T K g_b
+// Only the k(k+1)/2 pairs a <= b are formed (both matrices are symmetric).
+//
+// Scatter variants:
+//   atomic  - FP64 atomics into zeroed values (order not fixed)
+//   staged  - local matrices written structure-of-arrays, then one thread per
+//             CSR slot sums its contribution list in ascending element order
+//   blocked - one workgroup owns a contiguous block of rows whose values live
+//             in LDS; it recomputes every element touching the block and
+//             writes the block once.  Entries with at most two contributions
+//             are added in any order (exact); the others in a fixed order:
+//             from per-contribution side slots summed in element order
+//             (curves, surfaces, planar meshes, where only diagonals have
+//             more), or colour by colour (tetrahedra; elements of one colour
+//             share no node).
+#pragma once
+
+#include <cmath>
+
+#include <map>
+#include <tuple>
+#include <type_traits>
+
+#include "side.hpp"
+
+namespace lfem {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// atomic variant: one thread per element, values added to the global CSR
+// values with FP64 atomics (formed pair by pair, or accumulated point by point
+// for tetrahedra)
+// ---------------------------------------------------------------------------
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                                const int32_t *__restrict__ row_ptr,
+                                                const uint8_t *__restrict__ off8, int kkp)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    constexpr int NMAT = NM + (HA ? 1 : 0);
+    int32_t nid[E::k];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
+    double x[E::n][E::k];
+    gather_coords<E>(nid, g.coords, g.N, x);
+    const uint8_t *o = off8 + e * kkp;
+    if constexpr (E::d == 3) {
+        // tetrahedra: accumulate the local matrices point by point (see k_stage)
+        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
+        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+#pragma unroll
+        for (int a = 0; a < E::k; ++a) {
+            const int32_t rb = row_ptr[nid[a]];
+#pragma unroll
+            for (int b = 0; b < E::k; ++b)
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat)
+                    unsafeAtomicAdd(g.v[mat] + rb + o[a * E::k + b], local_value<E, NM, HA>(mat, a, b, LM, LA));
+        }
+        return;
+    }
+    double f[NM > 0 ? NM : 1][Q];
+    double kq[HA ? Q : 1][E::nsym];
+    const int bad = side_qdata<E, Q, NM, HA, kCoefRuntime>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
+    if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+    int p = 0;
+#pragma unroll
+    for (int a = 0; a < E::k; ++a)
+#pragma unroll
+        for (int b = a; b < E::k; ++b, ++p) {
+            double v[NMAT];
+            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
+            const int32_t sa = row_ptr[nid[a]] + o[a * E::k + b];
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sa, v[mat]);
+            if (a != b) {
+                const int32_t sb = row_ptr[nid[b]] + o[b * E::k + a];
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sb, v[mat]);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// staged variant: one thread per element writes its local values, structure
+// of arrays stage[(mat * np + p) * T + e]
+// ---------------------------------------------------------------------------
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                               double *__restrict__ stage)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    constexpr int NMAT = NM + (HA ? 1 : 0);
+    int32_t nid[E::k];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
+    double x[E::n][E::k];
+    gather_coords<E>(nid, g.coords, g.N, x);
+    if constexpr (E::d == 3) {
+        // tetrahedra: the Q-point data of 11 points (77 doubles) outweighs the
+        // local matrices, so accumulate those point by point instead
+        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
+        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+#pragma unroll
+        for (int p = 0; p < E::np; ++p)
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat)
+                stage[(mat * E::np + p) * T + e] = mat < NM ? LM[mat][p] : LA[p];
+    } else {
+        double f[NM > 0 ? NM : 1][Q];
+        double kq[HA ? Q : 1][E::nsym];
+        const int bad = side_qdata<E, Q, NM, HA, kCoefRuntime>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+#pragma unroll
+        for (int p = 0; p < E::np; ++p) {
+            double v[NMAT];
+            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat) stage[(mat * E::np + p) * T + e] = v[mat];
+        }
+    }
+}
+
+template <int K, int NMAT>
+__global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
+                                                const int32_t *__restrict__ cptr,
+                                                const int32_t *__restrict__ clist,
+                                                const double *__restrict__ stage,
+                                                double *__restrict__ v0, double *__restrict__ v1,
+                                                double *__restrict__ v2)
+{
+    constexpr int NP = K * (K + 1) / 2;
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= nnz) return;
+    double acc[NMAT];
+#pragma unroll
+    for (int mat = 0; mat < NMAT; ++mat) acc[mat] = 0.0;
+    const int32_t b = cptr[s], end = cptr[s + 1];
+    for (int32_t c = b; c < end; ++c) {
+        const int32_t code = clist[c];
+        const int64_t e = code >> 7;
+        const int ab = code & 127;
+        const int a = ab / K, bb = ab - a * K;
+        const int p = pair_index<K>(a, bb);
+#pragma unroll
+        for (int mat = 0; mat < NMAT; ++mat) acc[mat] += stage[(mat * NP + p) * T + e];
+    }
+    double *outs[3] = {v0, v1, v2};
+#pragma unroll
+    for (int mat = 0; mat < NMAT; ++mat) outs[mat][s] = acc[mat];
+}
+
+template <class E, int NM, bool HA, int NT>
+__global__ __launch_bounds__(NT) void k_blocked(const BlockArgs g)
+{
+    extern __shared__ double lds[];
+    blocked_block<E, NM, HA, NT>(g, xcd_block(blockIdx.x, g.nb), lds);
+}
+
+// Persistent side-slot kernel: workgroup w handles the blocks whose launch
+// order index is w, w + G, w + 2G, ... (G = gridDim.x, a multiple of 8 when
+// smaller than the block count, so every block of one workgroup lies in the
+// range of its XCD).  The next block's loads overlap the current block:
+//  - EARLY (a compile-time coefficient set and blocks of one chunk, which
+//    leaves registers for it): its record and element words are loaded
+//    before the current compute, its coordinates right after it;
+//  - otherwise its record and element words right after the current compute,
+//    its coordinates after the current write-out has been issued.
+// Loads complete in order, so waiting for one also waits for every load
+// issued before it; the explicit waits below keep the next block's loads out
+// of the current block's waits.
+template <class E, int Q, int NM, bool HA, int CF, int NT, bool MULTI>
+__global__ __launch_bounds__(NT) void k_side(const BlockArgs g, int rs)
+{
+    constexpr int NMAT = NM + (HA ? 1 : 0);
+    constexpr bool EARLY = CF != kCoefRuntime && !MULTI;
+    extern __shared__ double lds[];
+    for (int i = threadIdx.x; i < NMAT * rs; i += NT) lds[i] = 0.0;
+    __syncthreads();
+    int vb = blockIdx.x;
+    SideBlock<E> s;
+    side_load_rec<E>(g, xcd_block(vb, g.nb), s);
+    side_load_first<E>(g, s);
+    side_load_coords<E>(g, s);
+    for (;;) {
+        const int vn = vb + static_cast<int>(gridDim.x);
+        const bool more = vn < g.nb;
+        SideBlock<E> nxt;
+        if constexpr (EARLY) {
+            // this block's loads (and the previous write-out) complete here
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+            if (more) {
+                side_load_rec<E>(g, xcd_block(vn, g.nb), nxt);
+                side_load_first<E>(g, nxt);
+            }
+        }
+        const int bad = side_compute<E, Q, NM, HA, CF, NT, MULTI>(g, s, lds, g.cap, rs);
+        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+        if constexpr (EARLY) {
+            if (more) side_load_coords<E>(g, nxt);
+        } else {
+            // this block's ordered-entry records resident before the next loads
+            asm volatile("" ::"v"(s.ord0), "v"(s.ord1));
+            if (more) {
+                side_load_rec<E>(g, xcd_block(vn, g.nb), nxt);
+                side_load_first<E>(g, nxt);
+            }
+        }
+        __syncthreads();
+        side_reduce<E, NMAT, NT>(g, s, lds, rs);
+        __syncthreads();
+        side_write<NMAT, NT>(g, s.base, s.nloc, lds, rs);
+        if (!more) break;
+        if constexpr (!EARLY) side_load_coords<E>(g, nxt);
+        __syncthreads();
+        s = nxt;
+        vb = vn;
+    }
+}
+
+__global__ void k_fill_zero(double *__restrict__ x, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+inline unsigned grid_for(int64_t n, int nt) { return static_cast<unsigned>((n + nt - 1) / nt); }
+
+struct Outs {
+    const double *cm0 = nullptr, *cm1 = nullptr, *ca = nullptr;
+    double *v[3] = {nullptr, nullptr, nullptr};
+    int nm = 0;
+    bool ha = false;
+};
+
+Outs arrange(const NumericOut &o)
+{
+    Outs r;
+    if (o.what & LFEM_M) {
+        r.v[r.nm] = o.vals_m;
+        if (r.nm == 0) r.cm0 = nullptr; else r.cm1 = nullptr;
+        ++r.nm;
+    }
+    if (o.what & LFEM_MC) {
+        r.v[r.nm] = o.vals_mc;
+        if (r.nm == 0) r.cm0 = o.coef_c; else r.cm1 = o.coef_c;
+        ++r.nm;
+    }
+    if (o.what & LFEM_A) {
+        r.ha = true;
+        r.v[r.nm] = o.vals_a;
+        r.ca = o.coef_a;
+    }
+    return r;
+}
+
+// the two rules of each element dimension (points: segment 2, 3; triangle
+// 3, 6; tetrahedron 4, 11) as compile-time constants
+template <class E, class F>
+void with_rule(int Q, F &&fn)
+{
+    constexpr int QA = E::d == 1 ? 2 : (E::d == 2 ? 3 : 4);
+    constexpr int QB = E::d == 1 ? 3 : (E::d == 2 ? 6 : 11);
+    if (Q == QA) return fn(std::integral_constant<int, QA>{});
+    if (Q == QB) return fn(std::integral_constant<int, QB>{});
+    throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
+}
+
+template <class E, int NM, bool HA, int NT>
+void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
+template <class E, int NM, bool HA, int NT>
+void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
+
+template <class E, int NM, bool HA>
+void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
+{
+    constexpr int NMAT = NM + (HA ? 1 : 0);
+    if (m.T == 0 || p.nnz == 0) {
+        for (int mat = 0; mat < NMAT; ++mat)
+            if (p.nnz > 0) {
+                k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
+            }
+        return;
+    }
+    if (variant == LFEM_SCATTER_ATOMIC) {
+        for (int mat = 0; mat < NMAT; ++mat)
+            k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_atomic<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.row_ptr,
+                                                                                       p.off8, p.kkp);
+        });
+        LFEM_HIP(hipGetLastError());
+        return;
+    }
+    if (variant == LFEM_SCATTER_STAGED) {
+        build_staged(m, p, s);
+        const size_t need = static_cast<size_t>(NMAT) * E::np * m.T * sizeof(double);
+        if (p.stage_bytes < need) {
+            dev_free(p.stage);
+            p.stage = nullptr;
+            p.stage_bytes = 0;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
+            p.stage_bytes = need;
+        }
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_stage<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.stage);
+        });
+        LFEM_HIP(hipGetLastError());
+        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, m.T, p.cptr, p.clist,
+                                                                   p.stage, o.v[0], o.v[1], o.v[2]);
+        LFEM_HIP(hipGetLastError());
+        return;
+    }
+    // blocked
+    LFEM_REQUIRE(p.sched.nb > 0, LFEM_EUNSUPPORTED, "pattern has no block schedule");
+    constexpr int NT = kSideThreads;
+    const bool side = p.sched.side_mode;
+    const size_t lds = side ? side_lds_bytes(NMAT, p.sched.cap, p.max_row) : block_lds_bytes(p, NMAT);
+    LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "block schedule exceeds LDS");
+    if (side) {
+        if constexpr (E::d <= 2) return launch_side<E, NM, HA, NT>(m, p, o, lds, s);
+        throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
+    }
+    return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
+}
+
+// allow more than 64 KB of dynamic LDS for kern (once per size increase)
+void allow_lds(const void *kern, size_t lds)
+{
+    static thread_local std::map<const void *, size_t> granted;
+    size_t &g = granted[kern];
+    if (lds > 64 * 1024 && lds > g) {
+        LFEM_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        g = lds;
+    }
+}
+
+// workgroups of kern that are resident on the device at once
+int resident_groups(const void *kern, int nt, size_t lds)
+{
+    static thread_local std::map<std::tuple<const void *, size_t, int>, int> known;
+    int dev = 0;
+    LFEM_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(kern, lds, dev);
+    auto it = known.find(key);
+    if (it != known.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    LFEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
+    LFEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LFEM_REQUIRE(per_cu > 0, LFEM_EUNSUPPORTED, "block kernel does not fit on a compute unit");
+    const int r = per_cu * cus;
+    known.emplace(key, r);
+    return r;
+}
+
+template <class E, int NM, bool HA, int NT>
+void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
+{
+    auto kern = k_blocked<E, NM, HA, NT>;
+    allow_lds(reinterpret_cast<const void *>(kern), lds);
+    kern<<<p.sched.nb, NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]));
+    LFEM_HIP(hipGetLastError());
+}
+
+template <class E, int Q, int NM, bool HA, int CF, int NT, bool MULTI>
+void launch_side_q(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
+{
+    auto kern = k_side<E, Q, NM, HA, CF, NT, MULTI>;
+    const void *kp = reinterpret_cast<const void *>(kern);
+    allow_lds(kp, lds);
+    int grid = resident_groups(kp, NT, lds);
+    if (grid >= p.sched.nb) grid = p.sched.nb;
+    else grid &= ~7;  // keep each workgroup on the XCD its block range belongs to
+    kern<<<std::max(grid, 1), NT, lds, s>>>(block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]),
+                                            side_region(p.sched.cap, p.max_row));
+    LFEM_HIP(hipGetLastError());
+}
+
+// the coefficient set of the selected outputs as a compile-time constant:
+// bit 0 / 1: mass-class slot 0 / 1 is weighted, bit 2: the stiffness is
+template <int NM, bool HA, class F>
+void with_coef(const Outs &o, F &&fn)
+{
+    const int cf = (o.cm0 ? 1 : 0) | (o.cm1 ? 2 : 0) | (o.ca ? 4 : 0);
+    auto pick = [&](auto c) {
+        constexpr int C = decltype(c)::value;
+        constexpr bool ok = (NM >= 1 || !(C & 1)) && (NM == 2 || !(C & 2)) && (NM != 2 || (C & 3) == 2) &&
+                            (HA || !(C & 4));
+        if constexpr (ok) fn(c);
+        else throw Error{LFEM_EINVAL, "coefficient set does not match the selected matrices"};
+    };
+    switch (cf) {
+    case 0: return pick(std::integral_constant<int, 0>{});
+    case 1: return pick(std::integral_constant<int, 1>{});
+    case 2: return pick(std::integral_constant<int, 2>{});
+    case 4: return pick(std::integral_constant<int, 4>{});
+    case 5: return pick(std::integral_constant<int, 5>{});
+    case 6: return pick(std::integral_constant<int, 6>{});
+    default: throw Error{LFEM_EINVAL, "coefficient set does not match the selected matrices"};
+    }
+}
+
+template <class E, int NM, bool HA, int NT>
+void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
+{
+    // blocks of more than NT elements (P1 meshes) take the chunk loop and
+    // decide coefficients at run time; P2 blocks of one chunk get a
+    // compile-time coefficient set
+    const bool multi = E::p == 1 || p.sched.max_elems > NT;
+    with_rule<E>(m.Q, [&](auto qc) {
+        constexpr int Q = decltype(qc)::value;
+        if constexpr (E::p == 1) {
+            launch_side_q<E, Q, NM, HA, kCoefRuntime, NT, true>(m, p, o, lds, s);
+        } else {
+            if (multi) return launch_side_q<E, Q, NM, HA, kCoefRuntime, NT, true>(m, p, o, lds, s);
+            with_coef<NM, HA>(o, [&](auto cc) {
+                launch_side_q<E, Q, NM, HA, decltype(cc)::value, NT, false>(m, p, o, lds, s);
+            });
+        }
+    });
+}
+
+template <class E>
+void run_type(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
+{
+    switch (o.nm * 2 + (o.ha ? 1 : 0)) {
+    case 1: run<E, 0, true>(m, p, o, variant, s); break;
+    case 2: run<E, 1, false>(m, p, o, variant, s); break;
+    case 3: run<E, 1, true>(m, p, o, variant, s); break;
+    case 4: run<E, 2, false>(m, p, o, variant, s); break;
+    case 5: run<E, 2, true>(m, p, o, variant, s); break;
+    default: throw Error{LFEM_EINVAL, "no matrix selected"};
+    }
+}
+
+}  // namespace
+
+}  // namespace lfem

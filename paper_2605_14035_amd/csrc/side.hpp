@@ -99,6 +99,8 @@ __device__ __forceinline__ void side_load_first(const BlockArgs &g, SideBlock<E>
 {
     const int32_t tid = threadIdx.x;
     if (s.e0 + tid < s.e1) side_load_elem<E>(g, s.e0 + tid, s.nid, s.ow, s.nw);
+    s.ord0 = 0;
+    s.ord1 = 0;
     if (s.o0 + tid < s.o1) {
         s.ord0 = g.bord[2 * static_cast<int64_t>(s.o0 + tid)];
         s.ord1 = g.bord[2 * static_cast<int64_t>(s.o0 + tid) + 1];
@@ -111,10 +113,23 @@ __device__ __forceinline__ void side_load_coords(const BlockArgs &g, SideBlock<E
     if (s.e0 + static_cast<int32_t>(threadIdx.x) < s.e1) gather_coords<E>(s.nid, g.coords, g.N, s.x);
 }
 
+// Which outputs carry a nodal coefficient: bit s (s < NM) for mass-class slot
+// s, bit 2 for the stiffness; kCoefRuntime: decided from the pointers at run
+// time.  A compile-time set keeps the unused coefficient paths out of the
+// register allocation.
+constexpr int kCoefRuntime = -1;
+
+template <int CF>
+__device__ __forceinline__ bool has_coef(int bit, const double *ptr)
+{
+    if constexpr (CF == kCoefRuntime) return ptr != nullptr;
+    else return (CF >> bit) & 1;
+}
+
 // Q-point data of one element; returns the number of degenerate points.  The
 // geometry pass keeps only w_q mu_q and K_q per point; nodal coefficients are
 // interpolated afterwards so that they are not live during the geometry.
-template <class E, int Q, int NM, bool HA>
+template <class E, int Q, int NM, bool HA, int CF>
 __device__ __forceinline__ int side_qdata(const int32_t (&nid)[E::k], const double (&x)[E::n][E::k],
                                           const double *__restrict__ tab, const double *__restrict__ cm0,
                                           const double *__restrict__ cm1, const double *__restrict__ ca,
@@ -157,7 +172,7 @@ __device__ __forceinline__ int side_qdata(const int32_t (&nid)[E::k], const doub
         }
     };
     if constexpr (HA) {
-        if (ca) {
+        if (has_coef<CF>(2, ca)) {
             double ah[Q];
             interp(ca, ah);
 #pragma unroll
@@ -176,7 +191,7 @@ __device__ __forceinline__ int side_qdata(const int32_t (&nid)[E::k], const doub
     const double *cms[2] = {cm0, cm1};
 #pragma unroll
     for (int s = 0; s < NM; ++s) {
-        if (cms[s]) {
+        if (has_coef<CF>(s, cms[s])) {
             interp(cms[s], f[s]);
 #pragma unroll
             for (int q = 0; q < Q; ++q) f[s][q] = wmu[q] * f[s][q];
@@ -273,7 +288,7 @@ __device__ __forceinline__ void side_pairs(const double (&f)[NM > 0 ? NM : 1][Q]
 }
 
 // one element: row starts of its nodes in the block, Q-point data, pairs
-template <class E, int Q, int NM, bool HA>
+template <class E, int Q, int NM, bool HA, int CF>
 __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const int32_t (&nid)[E::k],
                                             const double (&x)[E::n][E::k],
                                             const uint32_t (&ow)[SideLayout<E>::KW], const uint32_t (&nw)[E::k],
@@ -288,7 +303,7 @@ __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const 
     }
     double f[NM > 0 ? NM : 1][Q];
     double kq[HA ? Q : 1][E::nsym];
-    const int bad = side_qdata<E, Q, NM, HA>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
+    const int bad = side_qdata<E, Q, NM, HA, CF>(nid, x, g.tab, g.cm0, g.cm1, g.ca, f, kq);
     // keep the pair sums out of the geometry phase (starting them early would
     // hold every pair's partial sums in registers)
     __builtin_amdgcn_sched_barrier(0);
@@ -300,13 +315,13 @@ __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const 
 // number of degenerate quadrature points met.  With MULTI, elements beyond the
 // first NT of the list are loaded here, with their own registers; without it
 // the block must hold at most NT elements.
-template <class E, int Q, int NM, bool HA, int NT, bool MULTI>
+template <class E, int Q, int NM, bool HA, int CF, int NT, bool MULTI>
 __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
                                             int rs)
 {
     const int tid = threadIdx.x;
     int bad = 0;
-    if (s.e0 + tid < s.e1) bad += side_element<E, Q, NM, HA>(g, s.nloc, s.nid, s.x, s.ow, s.nw, lds, dump, rs);
+    if (s.e0 + tid < s.e1) bad += side_element<E, Q, NM, HA, CF>(g, s.nloc, s.nid, s.x, s.ow, s.nw, lds, dump, rs);
     if constexpr (MULTI)
     for (int32_t c0 = s.e0 + NT; c0 < s.e1; c0 += NT) {
         const int32_t idx = c0 + tid;
@@ -316,7 +331,7 @@ __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<
             double x[E::n][E::k];
             side_load_elem<E>(g, idx, nid, ow, nw);
             gather_coords<E>(nid, g.coords, g.N, x);
-            bad += side_element<E, Q, NM, HA>(g, s.nloc, nid, x, ow, nw, lds, dump, rs);
+            bad += side_element<E, Q, NM, HA, CF>(g, s.nloc, nid, x, ow, nw, lds, dump, rs);
         }
     }
     return bad;
@@ -369,12 +384,12 @@ __device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nlo
 // one block whose record, first elements and coordinates are loaded (or in
 // flight) in s.  LDS value entries must be all zero on entry (and no thread
 // may still be writing out a previous block) and are all zero on return.
-template <class E, int Q, int NM, bool HA, int NT>
+template <class E, int Q, int NM, bool HA, int CF, int NT>
 __device__ __forceinline__ void side_block(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
                                            int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
-    const int bad = side_compute<E, Q, NM, HA, NT, true>(g, s, lds, dump, rs);
+    const int bad = side_compute<E, Q, NM, HA, CF, NT, true>(g, s, lds, dump, rs);
     if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
     __syncthreads();
     side_reduce<E, NMAT, NT>(g, s, lds, rs);
