@@ -30,8 +30,8 @@ METRIC = "elements/s for M+A assembly (P2 surface), % HBM roofline, batched vs p
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
 
-KERNEL_SOURCES = ("numeric.hip", "side.hpp", "blocked.hpp", "element.hpp", "symbolic.hip",
-                  "lfem_internal.hpp")
+KERNEL_SOURCES = ("numeric_impl.hpp", "numeric_surface.hip", "side.hpp", "blocked.hpp", "element.hpp",
+                  "symbolic.hip", "lfem_internal.hpp")
 KERNEL_NAME = "k_side<P2 surface, Q=6, M, A>"
 
 

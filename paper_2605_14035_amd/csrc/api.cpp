@@ -354,7 +354,7 @@ lfem_status lfem_status_reset(lfem_mesh_t m, void *stream)
 void lfem_mesh_destroy(lfem_mesh_t m)
 {
     if (!m) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     release_mesh(*m);
     delete m;
 }
@@ -362,7 +362,7 @@ void lfem_mesh_destroy(lfem_mesh_t m)
 void lfem_pattern_destroy(lfem_pattern_t p)
 {
     if (!p) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     release_pattern(*p);
     delete p;
 }

@@ -13,24 +13,41 @@ namespace lfem {
 
 namespace {
 
+// a pair of timing events, released on every exit path
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair()
+    {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            release();
+            throw Error{LFEM_EHIP, "hipEventCreate failed"};
+        }
+    }
+    ~EventPair() { release(); }
+    void release()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        a = b = nullptr;
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+};
+
 float time_variant(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s)
 {
-    hipEvent_t a, b;
-    LFEM_HIP(hipEventCreate(&a));
-    LFEM_HIP(hipEventCreate(&b));
+    EventPair ev;
     launch_numeric(m, p, o, variant, s);  // warm-up (builds lazy structures)
     float best = 1e30f;
     for (int r = 0; r < 3; ++r) {
-        LFEM_HIP(hipEventRecord(a, s));
+        LFEM_HIP(hipEventRecord(ev.a, s));
         launch_numeric(m, p, o, variant, s);
-        LFEM_HIP(hipEventRecord(b, s));
-        LFEM_HIP(hipEventSynchronize(b));
+        LFEM_HIP(hipEventRecord(ev.b, s));
+        LFEM_HIP(hipEventSynchronize(ev.b));
         float ms = 0.f;
-        LFEM_HIP(hipEventElapsedTime(&ms, a, b));
+        LFEM_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         best = std::min(best, ms);
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
     return best;
 }
 

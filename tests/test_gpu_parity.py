@@ -36,6 +36,34 @@ def say(*a):
     sys.stdout.flush()
 
 
+# every selection of matrices and coefficients (the side-slot kernels are
+# specialised on which outputs carry a coefficient)
+SELECTIONS = ["M", "A", "MC", "Aa", "M+A", "M+MC", "MC+Aa", "M+Aa", "M+MC+A", "M+MC+Aa", "A+MC"]
+
+
+@pytest.mark.parametrize("t", [t for t in meshgen.ALL_TYPES if t[1] <= 2 and t[2] == 2])
+@pytest.mark.parametrize("sel", SELECTIONS)
+def test_matrix_and_coefficient_selections(lf, t, sel):
+    m = meshgen.small_mesh(*t, size=3)
+    say("case", t, sel)
+    dm = lf.DeviceMesh.from_dict(m)
+    parts = sel.split("+")
+    what = ((lf.LFEM_M if "M" in parts else 0) | (lf.LFEM_MC if "MC" in parts else 0) |
+            (lf.LFEM_A if ("A" in parts or "Aa" in parts) else 0))
+    ca = torch.as_tensor(m["coef_a"], device="cuda") if "Aa" in parts else None
+    cc = torch.as_tensor(m["coef_c"], device="cuda") if "MC" in parts else None
+    out = dm.assemble(what, coef_a=ca, coef_c=cc, scatter=lf.LFEM_SCATTER_BLOCKED)
+    rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
+    refs = {"M": ("M", oracle.assemble(m, "mass")),
+            "MC": ("MC", oracle.assemble(m, "mass", coef=m["coef_c"])),
+            "A": ("A", oracle.assemble(m, "stiffness")),
+            "Aa": ("A", oracle.assemble(m, "stiffness", coef=m["coef_a"]))}
+    for part in parts:
+        key, ref = refs[part]
+        assert_csr_close(rp, ci, out[key].cpu().numpy(), ref, what=f"{t} {sel} {part}")
+    dm.close()
+
+
 @pytest.mark.parametrize("t", meshgen.ALL_TYPES)
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_small_all_types(lf, t, variant):
