@@ -70,8 +70,9 @@ def lib(long_double: bool = False):
                                     dp, dp, C.c_double, dp]
         L.oracle_shape_grad.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp,
                                         C.c_double, dp, dp, C.c_double, dp]
+        L.oracle_load.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp]
         for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
-                  L.oracle_energy, L.oracle_shape_grad):
+                  L.oracle_energy, L.oracle_shape_grad, L.oracle_load):
             f.restype = ci
         _libs[key] = L
     return _libs[key]
@@ -177,6 +178,17 @@ def energy(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0, long_double=False):
                              _ptr(out, C.c_double))
     _check(st, "energy")
     return float(out[0])
+
+
+def load(mesh, f=None, rule=None, long_double=False):
+    """Load vector b_j = sum_E sum_q w mu f_h phi_j, (N,); f: nodal values or
+    None for f = 1."""
+    args, keep, N, T, k = _mesh_args(mesh, *(rule or (None, None)))
+    f = _f64(f)
+    b = np.zeros(N)
+    st = lib(long_double).oracle_load(*args, _ptr(f, C.c_double), _ptr(b, C.c_double))
+    _check(st, "load")
+    return b
 
 
 def shape_grad(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):

@@ -524,3 +524,40 @@ int oracle_shape_grad(int surface, int d, int p, int Q, const double *qp, const 
     }
     return bad ? OR_EDEGENERATE : OR_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* load vector                                                              */
+/* ---------------------------------------------------------------------- */
+/*
+ * b[j] = sum_E sum_q w_q mu_E(xi_q) f_h(xi_q) phi_j(xi_q), the right-hand side
+ * that the paper's assembly returns beside M and A (section 6.1; summed node
+ * by node like the accumarray step of Listing 1).  f_h = sum_r f_r phi_r is
+ * the nodal data interpolated with the element basis; f NULL means f = 1.
+ * Contributions are added in element order.  b has N entries, overwritten.
+ */
+int oracle_load(int surface, int d, int p, int Q, const double *qp, const double *qw, int64_t N,
+                const double *coords, int64_t T, const int32_t *conn, const double *f, double *b)
+{
+    etype t;
+    int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
+    int64_t e, i;
+    real *acc;
+    if (st) return st;
+    acc = (real *)calloc((size_t)(N > 0 ? N : 1), sizeof(real));
+    if (!acc) return OR_ENOMEM;
+    for (e = 0; e < T; e++) {
+        real x[KMAX * DMAX], phi[KMAX], gp[KMAX * DMAX], fe[KMAX];
+        int a, q;
+        gather(&t, N, coords, T, conn, e, x);
+        for (a = 0; a < t.k; a++) fe[a] = f ? f[conn[(int64_t)a * T + e]] : 1.0;
+        for (q = 0; q < t.Q; q++) {
+            real mu, fh = 0.0;
+            if (point_geometry(&t, x, q, phi, gp, &mu)) bad = 1;
+            for (a = 0; a < t.k; a++) fh += fe[a] * phi[a];
+            for (a = 0; a < t.k; a++) acc[conn[(int64_t)a * T + e]] += t.qw[q] * mu * fh * phi[a];
+        }
+    }
+    for (i = 0; i < N; i++) b[i] = (double)acc[i];
+    free(acc);
+    return bad ? OR_EDEGENERATE : OR_OK;
+}
