@@ -206,6 +206,18 @@ lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double 
                         const double *w, const double *z, double beta, double *J_out,
                         void *stream);
 
+/*
+ * Load vector (the right-hand side the paper's assembly returns beside M and
+ * A, section 6.1):
+ *     b[j] = sum_E sum_q w_q mu_E(xi_q) f_h(xi_q) phi_j(xi_q),
+ * f_h = sum_r f_r phi_r the nodal data coef_f [N] interpolated with the
+ * element basis (NULL: f = 1, so b = M 1).  b: N doubles, overwritten.  Each
+ * element's contributions are staged and summed per node in ascending
+ * element order (bitwise reproducible).  Uses the mesh's scratch buffer:
+ * calls on one mesh must not overlap.
+ */
+lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, void *stream);
+
 /* Number of degenerate (element, quadrature point) evaluations seen by this
  * mesh since creation or the last reset.  SYNCHRONISES the device. */
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate);

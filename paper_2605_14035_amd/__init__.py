@@ -26,7 +26,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -179,6 +179,12 @@ def lfem_energy(mesh, u, v, alpha, w, z, beta, J_out, stream=None):
                         float(alpha), _ptr(w, torch.float64, "w"), _ptr(z, torch.float64, "z"),
                         float(beta), _ptr(J_out, torch.float64, "J_out"), _stream(stream))
     _lib.check(st, "lfem_energy")
+
+
+def lfem_assemble_load(mesh, coef_f, b, stream=None):
+    st = _L.lfem_assemble_load(mesh, _ptr(coef_f, torch.float64, "coef_f"), _ptr(b, torch.float64, "b"),
+                               _stream(stream))
+    _lib.check(st, "lfem_assemble_load")
 
 
 def lfem_status_get(mesh) -> int:

@@ -14,6 +14,10 @@
 // Element contributions are staged per (local node, component) and gathered
 // per node over its ascending incidence list, so the result is bitwise
 // reproducible.
+//
+// The load vector b_j = sum_E sum_q w_q mu f_h(xi_q) phi_j(xi_q) (the
+// right-hand side of the paper's assembly, section 6.1) is staged and
+// gathered the same way.
 #include <cmath>
 
 #include "element.hpp"
@@ -137,6 +141,47 @@ __global__ __launch_bounds__(256) void k_adjoint(
     }
 }
 
+// per (local node a) load contributions into out[a*T + e]; f NULL: f = 1
+template <class E>
+__global__ __launch_bounds__(256) void k_load(const double *__restrict__ coords, const int32_t *__restrict__ conn,
+                                              const double *__restrict__ tab, int64_t N, int64_t T, int Q,
+                                              const double *__restrict__ f, double *__restrict__ out,
+                                              unsigned long long *__restrict__ degenerate)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    int32_t nid[E::k];
+    double x[E::n][E::k], fe[E::k], acc[E::k];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
+    gather_coords<E>(nid, coords, N, x);
+    double J0[E::n][E::d], H[E::n][E::nh > 0 ? E::nh : 1];
+    jacobian_setup<E>(x, J0, H);
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) {
+        fe[a] = f ? f[nid[a]] : 1.0;
+        acc[a] = 0.0;
+    }
+    int bad = 0;
+    for (int q = 0; q < Q; ++q) {
+        cdouble *t = const_table(tab) + q * E::stride;
+        double J[E::n][E::d];
+        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        double K[E::d][E::d], mu;
+        geometry<E>(J, K, mu);  // K unused: only the measure is needed
+        bad += !(mu > 0.0 && mu < INFINITY);
+        double fh = 0.0;
+#pragma unroll
+        for (int a = 0; a < E::k; ++a) fh = fma(fe[a], t[E::off_phi + a], fh);
+        const double wmf = t[0] * mu * fh;
+#pragma unroll
+        for (int a = 0; a < E::k; ++a) acc[a] = fma(wmf, t[E::off_phi + a], acc[a]);
+    }
+    if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) out[a * T + e] = acc[a];
+}
+
 // grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*n+c)*T + e]
 __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
                                                 const int32_t *__restrict__ ne_ptr,
@@ -212,6 +257,29 @@ void dispatch(Mesh &m, bool grad, const double *u, const double *v, double alpha
     }
 }
 
+template <class E>
+void run_load(Mesh &m, const double *f, double *out, hipStream_t s)
+{
+    if (m.T == 0) return;
+    k_load<E><<<grid_for(m.T, 256), 256, 0, s>>>(m.coords, m.conn, m.tab, m.N, m.T, m.Q, f, out, m.degenerate);
+    LFEM_HIP(hipGetLastError());
+}
+
+void dispatch_load(Mesh &m, const double *f, double *out, hipStream_t s)
+{
+    switch (m.etype) {
+    case S1P1: run_load<ET<1, 1, 1>>(m, f, out, s); break;
+    case S1P2: run_load<ET<1, 1, 2>>(m, f, out, s); break;
+    case S2P1: run_load<ET<1, 2, 1>>(m, f, out, s); break;
+    case S2P2: run_load<ET<1, 2, 2>>(m, f, out, s); break;
+    case B2P1: run_load<ET<0, 2, 1>>(m, f, out, s); break;
+    case B2P2: run_load<ET<0, 2, 2>>(m, f, out, s); break;
+    case B3P1: run_load<ET<0, 3, 1>>(m, f, out, s); break;
+    case B3P2: run_load<ET<0, 3, 2>>(m, f, out, s); break;
+    default: throw Error{LFEM_EUNSUPPORTED, "element type"};
+    }
+}
+
 }  // namespace
 
 double *mesh_scratch(Mesh &m, size_t bytes)
@@ -229,7 +297,7 @@ double *mesh_scratch(Mesh &m, size_t bytes)
 void launch_energy(Mesh &m, const double *u, const double *v, double alpha, const double *w,
                    const double *z, double beta, double *J, hipStream_t s)
 {
-    const int64_t chunk = 64 * 1024;
+    const int64_t chunk = 4096;
     const int64_t nblk = std::max<int64_t>(1, (m.T + chunk - 1) / chunk);
     double *buf = mesh_scratch(m, static_cast<size_t>(m.T + nblk + 1) * sizeof(double));
     double *part = buf + m.T;
@@ -243,6 +311,17 @@ void launch_energy(Mesh &m, const double *u, const double *v, double alpha, cons
     LFEM_HIP(hipGetLastError());
     k_reduce_sum<<<1, RED_NT, 0, s>>>(part, nblk, nblk, J);
     LFEM_HIP(hipGetLastError());
+}
+
+void launch_load(Mesh &m, const double *f, double *b, hipStream_t s)
+{
+    const size_t cnt = static_cast<size_t>(m.k) * m.T;
+    double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
+    dispatch_load(m, f, stage, s);
+    if (m.N > 0) {
+        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, 1, m.ne_ptr, m.ne, stage, b);
+        LFEM_HIP(hipGetLastError());
+    }
 }
 
 void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,

@@ -332,6 +332,14 @@ lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double 
     });
 }
 
+lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, void *stream)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(m && (b || m->N == 0), LFEM_EINVAL, "null mesh or b");
+        launch_load(*m, coef_f, b, S(stream));
+    });
+}
+
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate)
 {
     return guarded([&] {

@@ -195,5 +195,6 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
                        const double *w, const double *z, double beta, double *grad,
                        hipStream_t s);
 double *mesh_scratch(Mesh &m, size_t bytes);
+void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
 
 }  // namespace lfem

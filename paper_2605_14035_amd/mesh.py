@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFACE,
-               copy_from_device, lfem_assemble, lfem_energy, lfem_mesh_create,
+               copy_from_device, lfem_assemble, lfem_assemble_load, lfem_energy, lfem_mesh_create,
                lfem_mesh_destroy, lfem_mesh_set_coords, lfem_pattern_build,
                lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
 
@@ -80,6 +80,13 @@ class DeviceMesh:
         lfem_assemble(self.handle, self.pattern, what, coef_a, coef_c, out.get("M"),
                       out.get("A"), out.get("MC"), scatter, stream)
         return out
+
+    def load(self, f=None, out=None, stream=None):
+        """Load vector b_j = sum_E sum_q w mu f_h phi_j as a float64 (N,) tensor;
+        f: nodal values (N,) or None for f = 1."""
+        b = out if out is not None else torch.empty(self.N, dtype=torch.float64, device=self.coords.device)
+        lfem_assemble_load(self.handle, f, b, stream)
+        return b
 
     def degenerate_count(self):
         return lfem_status_get(self.handle)
