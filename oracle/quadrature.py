@@ -27,8 +27,8 @@ import numpy as np
 mp.mp.dps = 40
 
 # rule id = (simplex dimension, number of points) -> polynomial degree
-DEGREE = {(1, 1): 1, (1, 2): 3, (1, 3): 5, (1, 4): 7, (1, 5): 9,
-          (2, 1): 1, (2, 3): 2, (2, 6): 4,
+DEGREE = {(1, 1): 1, (1, 2): 3, (1, 3): 5, (1, 4): 7, (1, 5): 9, (1, 6): 11,
+          (2, 1): 1, (2, 3): 2, (2, 6): 4, (2, 16): 8,
           (3, 1): 1, (3, 4): 2, (3, 11): 4}
 
 
@@ -45,6 +45,10 @@ def _orbit(sym, params):
         a = params[0]
         b = 1 - 2 * a
         return [[a, a, b], [a, b, a], [b, a, a]]
+    if sym == "S111":
+        a, b = params
+        c = 1 - a - b
+        return [[a, b, c], [a, c, b], [b, a, c], [b, c, a], [c, a, b], [c, b, a]]
     if sym == "S4":
         return [[mp.mpf(1) / 4] * 4]
     if sym == "S31":
@@ -71,6 +75,44 @@ def _sym_moments_tri(lam):
 
 
 _TRI_EXACT = [mp.mpf(1) / 2, mp.mpf(1) / 4, mp.mpf(1) / 120, mp.mpf(1) / 10]
+
+
+# degree <= 8 invariants of the triangle's symmetry group: with sum l = 1 every
+# symmetric polynomial is a polynomial in e2 = l0 l1 + l0 l2 + l1 l2 and
+# e3 = l0 l1 l2; the monomials e2^a e3^b, 2a + 3b <= 8, span degree <= 8
+_TRI8 = [(a, b) for b in range(3) for a in range(5) if 2 * a + 3 * b <= 8]
+
+
+def _sym_moments_tri8(lam):
+    l0, l1, l2 = lam
+    e2 = l0 * l1 + l0 * l2 + l1 * l2
+    e3 = l0 * l1 * l2
+    return [e2 ** a * e3 ** b for a, b in _TRI8]
+
+
+def _tri_exact(a, b):
+    """int over the triangle (area 1/2) of e2^a e3^b, expanded into barycentric
+    monomials, each integrated exactly (Dirichlet integral)."""
+    from fractions import Fraction
+    from math import factorial
+    poly = {(0, 0, 0): Fraction(1)}
+    def mul(p, q):
+        out = {}
+        for ka, ca in p.items():
+            for kb, cb in q.items():
+                k = tuple(x + y for x, y in zip(ka, kb))
+                out[k] = out.get(k, 0) + ca * cb
+        return out
+    e2 = {(1, 1, 0): Fraction(1), (1, 0, 1): Fraction(1), (0, 1, 1): Fraction(1)}
+    e3 = {(1, 1, 1): Fraction(1)}
+    for _ in range(a):
+        poly = mul(poly, e2)
+    for _ in range(b):
+        poly = mul(poly, e3)
+    tot = Fraction(0)
+    for k, c in poly.items():
+        tot += c * Fraction(factorial(k[0]) * factorial(k[1]) * factorial(k[2]), factorial(sum(k) + 2))
+    return mp.mpf(tot.numerator) / tot.denominator
 
 
 def _sym_moments_tet(lam):
@@ -110,13 +152,28 @@ def _solve(orbits, moments, exact, x0):
     return pts, wts
 
 
+def _legendre(n, t):
+    """P_n(t) and P_n'(t) by the three-term recurrence."""
+    p0, p1 = mp.mpf(1), t
+    for k in range(2, n + 1):
+        p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+    dp = n * (t * p1 - p0) / (t ** 2 - 1)
+    return p1, dp
+
+
 def _gauss_legendre(n):
-    """n-point Gauss-Legendre on [0, 1]: roots of P_n by Newton."""
+    """n-point Gauss-Legendre on [0, 1]: roots of P_n by Newton's method from
+    the usual cosine estimates (one root per estimate)."""
     pts, wts = [], []
     for i in range(1, n + 1):
-        x0 = mp.cos(mp.pi * (i - mp.mpf(1) / 4) / (n + mp.mpf(1) / 2))
-        x = mp.findroot(lambda t: mp.legendre(n, t), x0)
-        dp = mp.diff(lambda t: mp.legendre(n, t), x)
+        x = mp.cos(mp.pi * (i - mp.mpf(1) / 4) / (n + mp.mpf(1) / 2))
+        for _ in range(100):
+            p, dp = _legendre(n, x)
+            step = p / dp
+            x -= step
+            if abs(step) < mp.mpf(10) ** -38:
+                break
+        _, dp = _legendre(n, x)
         w = 2 / ((1 - x ** 2) * dp ** 2)
         pts.append([(1 + x) / 2])
         wts.append(w / 2)
@@ -139,6 +196,18 @@ def _rule_mp(dim: int, npts: int):
         if npts == 6:
             return _solve([("S21", 1), ("S21", 1)], _sym_moments_tri, _TRI_EXACT,
                           [0.11, 0.44, 0.05, 0.09])
+        if npts == 16:
+            # degree 8: centroid + three S21 orbits + one S111 orbit, the
+            # structure of the 16-point rule the paper uses (Dunavant); the
+            # published values (weights summing to 1) only seed the iteration
+            seed = [0.144315607677787 / 2,
+                    0.095091634267285 / 2, 0.459292588292723,
+                    0.103217370534718 / 2, 0.170569307751760,
+                    0.032458497623198 / 2, 0.050547228317031,
+                    0.027230314174435 / 2, 0.008394777409958, 0.263112829634638]
+            exact = [_tri_exact(a, b) for a, b in _TRI8]
+            return _solve([("S3", 0), ("S21", 1), ("S21", 1), ("S21", 1), ("S111", 2)],
+                          _sym_moments_tri8, exact, seed)
     if dim == 3:
         if npts == 1:
             return _solve([("S4", 0)], lambda l: [mp.mpf(1)], [mp.mpf(1) / 6], [0.1])

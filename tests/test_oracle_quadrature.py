@@ -15,7 +15,7 @@ import pytest
 
 from oracle import quadrature as Q
 
-RULES = [(1, 2), (1, 3), (2, 1), (2, 3), (2, 6), (3, 1), (3, 4), (3, 11)]
+RULES = [(1, 2), (1, 3), (1, 5), (1, 6), (2, 1), (2, 3), (2, 6), (2, 16), (3, 1), (3, 4), (3, 11)]
 
 
 def exact_monomial(alpha):
@@ -88,3 +88,28 @@ def test_known_rule_values():
     P, W = Q.rule(3, 11)
     assert abs(W.min() * 6 + 148 / 1875) < 1e-15
     assert np.sum(W < 0) == 1
+
+
+def test_degree8_triangle_matches_published_rule():
+    """The 16-point degree-8 rule solved from the moment equations equals the
+    published 16-point rule (Dunavant, 1985) to the 15 digits printed there
+    (weights normalised to sum 1)."""
+    P, W = Q.rule(2, 16)
+    lam = np.column_stack([1 - P.sum(1), P])
+    W1 = 2 * W
+    published = [  # (weight, orbit of barycentric coordinates)
+        (0.144315607677787, (1 / 3, 1 / 3, 1 / 3)),
+        (0.095091634267285, (0.459292588292723, 0.459292588292723, 0.081414823414554)),
+        (0.103217370534718, (0.170569307751760, 0.170569307751760, 0.658861384496480)),
+        (0.032458497623198, (0.050547228317031, 0.050547228317031, 0.898905543365938)),
+        (0.027230314174435, (0.008394777409958, 0.263112829634638, 0.728492392955404)),
+    ]
+    seen = 0
+    for w, orbit in published:
+        perms = {tuple(np.round(p, 12)): p for p in itertools.permutations(orbit)}
+        for p in perms.values():
+            d = np.abs(lam - np.array(p)).max(1)
+            i = int(d.argmin())
+            assert d[i] < 2e-14 and abs(W1[i] - w) < 2e-14, (p, d[i], W1[i], w)
+            seen += 1
+    assert seen == 16
