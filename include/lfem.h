@@ -86,11 +86,16 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * n_amb * n_nodes entries and conn has k * n_elems entries, k = C(order+d, d).
  * quad_points selects the quadrature rule on the reference simplex by its
  * number of points (0: the default for the element type):
- *   segment: 2 (Gauss, degree 3, P1 default), 3 (Gauss, degree 5, P2 default)
- *   triangle: 3 (interior orbit, degree 2, P1 default), 6 (degree 4, P2 default)
+ *   segment: 2 (Gauss, degree 3, P1 default), 3 (Gauss, degree 5, P2 default),
+ *            5, 6 (Gauss, degree 9, 11)
+ *   triangle: 3 (interior orbit, degree 2, P1 default), 6 (degree 4, P2 default),
+ *            16 (Dunavant, degree 8)
  *   tetrahedron: 4 (degree 2, P1 default), 11 (degree 4, P2 default)
- * The rules are those of the paper's quadrature forms (section 3.2.2) with the
- * weights summing to the reference measure.  Builds the node -> element
+ * The rules are those of the paper's quadrature forms (section 3.2.2) and the
+ * high-order rules of its precomputations (section 5.2: Gauss of degree 10 or
+ * more on segments, Dunavant of degree 8 on triangles), with the weights
+ * summing to the reference measure.  Batched assembly takes the two default rules only.
+ * Builds the node -> element
  * incidence on the device (asynchronous on stream).
  * Errors: LFEM_EINVAL (sizes, nulls, n_elems * k >= 2^31),
  * LFEM_EUNSUPPORTED (type/rule), LFEM_ENOMEM, LFEM_EHIP.

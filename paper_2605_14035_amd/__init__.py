@@ -15,13 +15,16 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_ATOMIC, LFEM_SCATTER_AUTO,
-                   LFEM_SCATTER_BLOCKED, LFEM_SCATTER_STAGED, LFEM_SURFACE, LfemError)
+from ._lib import (LFEM_A, LFEM_BULK, LFEM_EDEGENERATE, LFEM_EHIP, LFEM_EINVAL, LFEM_ENOMEM,
+                   LFEM_ERANGE, LFEM_EUNSUPPORTED, LFEM_M, LFEM_MC, LFEM_OK, LFEM_SCATTER_ATOMIC,
+                   LFEM_SCATTER_AUTO, LFEM_SCATTER_BLOCKED, LFEM_SCATTER_STAGED, LFEM_SURFACE, LfemError)
 
 _L = _lib.load()
 
 __all__ = [
     "LFEM_A", "LFEM_BULK", "LFEM_M", "LFEM_MC", "LFEM_SCATTER_ATOMIC", "LFEM_SCATTER_AUTO",
+    "LFEM_OK", "LFEM_EINVAL", "LFEM_ENOMEM", "LFEM_EHIP", "LFEM_ERANGE", "LFEM_EDEGENERATE",
+    "LFEM_EUNSUPPORTED",
     "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LfemError",
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",

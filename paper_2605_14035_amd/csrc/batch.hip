@@ -107,7 +107,9 @@ BatchKernel pick_kernel(unsigned what)
 
 bool batch_eligible(const Mesh &m, const Pattern &p)
 {
-    return m.d <= 2 && (m.T == 0 || (p.sched.nb > 0 && p.sched.side_mode));
+    // the batch kernel is compiled for the two default rules of each dimension
+    const bool rule_ok = m.Q == (m.d == 1 ? 2 : 3) || m.Q == (m.d == 1 ? 3 : 6);
+    return m.d <= 2 && rule_ok && (m.T == 0 || (p.sched.nb > 0 && p.sched.side_mode));
 }
 
 void release_graph(lfem_batch_s &b)
@@ -293,8 +295,8 @@ lfem_status batch_create(int n, Mesh *const *meshes, Pattern *const *pats, unsig
         b->pats.assign(pats, pats + n);
         for (int i = 0; i < n; ++i)
             LFEM_REQUIRE(batch_eligible(*meshes[i], *pats[i]), LFEM_EUNSUPPORTED,
-                         "batched assembly covers curves, surfaces and planar meshes whose "
-                         "many-contribution entries are diagonal");
+                         "batched assembly covers curves, surfaces and planar meshes under the "
+                         "default rules, whose many-contribution entries are diagonal");
         LFEM_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         LFEM_HIP(hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming));
         LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b->counter), sizeof(int)));

@@ -270,8 +270,15 @@ Outs arrange(const NumericOut &o)
     return r;
 }
 
-// the two rules of each element dimension (points: segment 2, 3; triangle
-// 3, 6; tetrahedron 4, 11) as compile-time constants
+// the rules of each element dimension as compile-time constants: the two
+// defaults (points: segment 2, 3; triangle 3, 6; tetrahedron 4, 11) and the
+// high-order ones (segment 5, 6; triangle 16)
+template <class E>
+constexpr bool high_order_rule(int Q)
+{
+    return Q > (E::d == 1 ? 3 : (E::d == 2 ? 6 : 11));
+}
+
 template <class E, class F>
 void with_rule(int Q, F &&fn)
 {
@@ -279,6 +286,13 @@ void with_rule(int Q, F &&fn)
     constexpr int QB = E::d == 1 ? 3 : (E::d == 2 ? 6 : 11);
     if (Q == QA) return fn(std::integral_constant<int, QA>{});
     if (Q == QB) return fn(std::integral_constant<int, QB>{});
+    if constexpr (E::d == 1) {
+        if (Q == 5) return fn(std::integral_constant<int, 5>{});
+        if (Q == 6) return fn(std::integral_constant<int, 6>{});
+    }
+    if constexpr (E::d == 2) {
+        if (Q == 16) return fn(std::integral_constant<int, 16>{});
+    }
     throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
 }
 
@@ -422,12 +436,12 @@ template <class E, int NM, bool HA, int NT>
 void launch_side(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s)
 {
     // blocks of more than NT elements (P1 meshes) take the chunk loop and
-    // decide coefficients at run time; P2 blocks of one chunk get a
-    // compile-time coefficient set
+    // decide coefficients at run time, as do the high-order rules; P2 blocks
+    // of one chunk under a default rule get a compile-time coefficient set
     const bool multi = E::p == 1 || p.sched.max_elems > NT;
     with_rule<E>(m.Q, [&](auto qc) {
         constexpr int Q = decltype(qc)::value;
-        if constexpr (E::p == 1) {
+        if constexpr (E::p == 1 || high_order_rule<E>(Q)) {
             launch_side_q<E, Q, NM, HA, kCoefRuntime, NT, true>(m, p, o, lds, s);
         } else {
             if (multi) return launch_side_q<E, Q, NM, HA, kCoefRuntime, NT, true>(m, p, o, lds, s);

@@ -4,10 +4,17 @@
 //
 // Rules (weights sum to the reference measure: 1, 1/2, 1/6):
 //   segment      Gauss-Legendre with 2 points (degree 3) and 3 points (degree 5)
+//                in closed form; 5 and 6 points (degree 9, 11): the roots of
+//                the Legendre polynomial by Newton's method on its three-term
+//                recurrence, weights 2 / ((1 - t^2) P_n'(t)^2), mapped to [0, 1]
 //   triangle     3 points, degree 2: barycentric orbit of (2/3, 1/6, 1/6)
 //                6 points, degree 4: two orbits (a, a, 1-2a) with
 //                a = (8 - sqrt10 +- sqrt(38 - 44 sqrt(2/5))) / 18,
 //                weights (620 +- sqrt(213125 - 53320 sqrt10)) / 3720, times 1/2
+//                16 points, degree 8 (the high-order rule of sections 3.2.2, 5.2): the
+//                centroid, three orbits (a, a, 1-2a) and one orbit of six
+//                permutations (a, b, 1-a-b); Dunavant's published values to
+//                15 digits (area-one weights, times 1/2)
 //   tetrahedron  4 points, degree 2: orbit (a,a,a,1-3a), a = (5 - sqrt5)/20
 //                11 points, degree 4: centroid (-148/1875), orbit (1/14 x3, 11/14)
 //                (343/7500), orbit (a, a, 1/2-a, 1/2-a), a = (1 + sqrt(5/14))/4
@@ -36,10 +43,58 @@ void add_bary(Rule &r, std::initializer_list<double> lam, double w)
     r.w.push_back(w);
 }
 
+// n-point Gauss-Legendre rule on [0, 1]
+void gauss_legendre(int n, Rule &r)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            // P_n(t) and P_n'(t) from (j+1) P_{j+1} = (2j+1) t P_j - j P_{j-1}
+            double p0 = 1.0, p1 = t;
+            for (int j = 1; j < n; ++j) {
+                const double p2 = ((2.0 * j + 1.0) * t * p1 - j * p0) / (j + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-17) break;
+        }
+        r.pts.push_back({0.5 * (1.0 + t)});
+        r.w.push_back(1.0 / ((1.0 - t * t) * dp * dp));
+    }
+}
+
+void add_orbit21(Rule &r, double a, double w)
+{
+    const double b = 1.0 - 2.0 * a;
+    add_bary(r, {b, a, a}, w);
+    add_bary(r, {a, b, a}, w);
+    add_bary(r, {a, a, b}, w);
+}
+
+void add_orbit111(Rule &r, double a, double b, double w)
+{
+    const double c = 1.0 - a - b;
+    add_bary(r, {a, b, c}, w);
+    add_bary(r, {a, c, b}, w);
+    add_bary(r, {b, a, c}, w);
+    add_bary(r, {b, c, a}, w);
+    add_bary(r, {c, a, b}, w);
+    add_bary(r, {c, b, a}, w);
+}
+
 bool make_rule(int d, int npts, Rule &r)
 {
     r = Rule{};
     if (d == 1) {
+        if (npts == 5 || npts == 6) {
+            gauss_legendre(npts, r);
+            return true;
+        }
         if (npts == 2) {
             double s = 0.5 / std::sqrt(3.0);
             r.pts = {{0.5 - s}, {0.5 + s}};
@@ -68,12 +123,15 @@ bool make_rule(int d, int npts, Rule &r)
             const double wroot = std::sqrt(213125.0 - 53320.0 * s10);
             const double a[2] = {(8.0 - s10 + root) / 18.0, (8.0 - s10 - root) / 18.0};
             const double w[2] = {(620.0 + wroot) / 3720.0 * 0.5, (620.0 - wroot) / 3720.0 * 0.5};
-            for (int o = 0; o < 2; ++o) {
-                const double b = 1.0 - 2.0 * a[o];
-                add_bary(r, {b, a[o], a[o]}, w[o]);
-                add_bary(r, {a[o], b, a[o]}, w[o]);
-                add_bary(r, {a[o], a[o], b}, w[o]);
-            }
+            for (int o = 0; o < 2; ++o) add_orbit21(r, a[o], w[o]);
+            return true;
+        }
+        if (npts == 16) {
+            add_bary(r, {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0}, 0.5 * 0.144315607677787);
+            add_orbit21(r, 0.459292588292723, 0.5 * 0.095091634267285);
+            add_orbit21(r, 0.170569307751760, 0.5 * 0.103217370534718);
+            add_orbit21(r, 0.050547228317031, 0.5 * 0.032458497623198);
+            add_orbit111(r, 0.008394777409958, 0.263112829634638, 0.5 * 0.027230314174435);
             return true;
         }
         return false;
