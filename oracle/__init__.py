@@ -71,8 +71,9 @@ def lib(long_double: bool = False):
         L.oracle_shape_grad.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp,
                                         C.c_double, dp, dp, C.c_double, dp]
         L.oracle_load.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp]
+        L.oracle_kll.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, dp]
         for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
-                  L.oracle_energy, L.oracle_shape_grad, L.oracle_load):
+                  L.oracle_energy, L.oracle_shape_grad, L.oracle_load, L.oracle_kll):
             f.restype = ci
         _libs[key] = L
     return _libs[key]
@@ -189,6 +190,21 @@ def load(mesh, f=None, rule=None, long_double=False):
     st = lib(long_double).oracle_load(*args, _ptr(f, C.c_double), _ptr(b, C.c_double))
     _check(st, "load")
     return b
+
+
+def kll(mesh, nu, H=None, rule=None):
+    """Non-linear terms of the mean-curvature-flow example (section 6.2):
+    alpha^2 = |grad_Gamma_h nu_h|^2 (Frobenius), f_1[c] = int alpha^2 (nu_h)_c phi_j,
+    f_2 = int alpha^2 H_h phi_j.  nu: (n_amb, N) nodal vector field, H: (N,) or
+    None for 1.  Returns an (n_amb + 1, N) array: rows f_1 components, then f_2."""
+    args, keep, N, T, k = _mesh_args(mesh, *(rule or (None, None)))
+    n_amb = keep[2].shape[0]
+    nu = _f64(np.asarray(nu).reshape(n_amb, N))
+    H = _f64(H)
+    f = np.zeros((n_amb + 1, N))
+    st = lib().oracle_kll(*args, _ptr(nu, C.c_double), _ptr(H, C.c_double), _ptr(f, C.c_double))
+    _check(st, "kll")
+    return f
 
 
 def shape_grad(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):

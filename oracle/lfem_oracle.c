@@ -561,3 +561,59 @@ int oracle_load(int surface, int d, int p, int Q, const double *qp, const double
     free(acc);
     return bad ? OR_EDEGENERATE : OR_OK;
 }
+
+/* Non-linear terms of the mean-curvature-flow example (section 6.2, the
+ * vector f = (f_1; f_2)): for a nodal vector field nu (n components,
+ * nu[c*N + r]) and a nodal scalar H (NULL: H = 1),
+ *   alpha^2 = |grad_Gamma_h nu_h|^2  (Frobenius norm of the tangential
+ *             gradient; row c is grad_Gamma_h (nu_h)_c = sum_a nu_{c,a} grad phi_a)
+ *   f[c*N + j] = sum_E sum_q w mu alpha^2 (nu_h)_c phi_j      c < n  (f_1)
+ *   f[n*N + j] = sum_E sum_q w mu alpha^2 H_h phi_j                  (f_2)
+ * The steps follow the listing of that section: local nodal values, the
+ * gradient from the tangential basis gradients C^T [grad_hat phi; 0], its
+ * Frobenius norm squared, the weighted point values, then the products with
+ * phi_j summed over the points.  Contributions are added in element order. */
+int oracle_kll(int surface, int d, int p, int Q, const double *qp, const double *qw, int64_t N,
+               const double *coords, int64_t T, const int32_t *conn, const double *nu,
+               const double *H, double *f)
+{
+    etype t;
+    int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
+    int64_t e, i;
+    real *acc;
+    if (st) return st;
+    acc = (real *)calloc((size_t)(N > 0 ? N : 1) * (size_t)(t.n + 1), sizeof(real));
+    if (!acc) return OR_ENOMEM;
+    for (e = 0; e < T; e++) {
+        real x[KMAX * DMAX], phi[KMAX], gp[KMAX * DMAX], ul[KMAX][DMAX + 1];
+        int a, c, r, q;
+        gather(&t, N, coords, T, conn, e, x);
+        for (a = 0; a < t.k; a++) {
+            int64_t g = conn[(int64_t)a * T + e];
+            for (c = 0; c < t.n; c++) ul[a][c] = nu[(int64_t)c * N + g];
+            ul[a][t.n] = H ? H[g] : 1.0;
+        }
+        for (q = 0; q < t.Q; q++) {
+            real mu, alpha2 = 0.0, uh[DMAX + 1], wgt;
+            if (point_geometry(&t, x, q, phi, gp, &mu)) bad = 1;
+            for (c = 0; c < t.n; c++)
+                for (r = 0; r < t.n; r++) {
+                    real gcr = 0.0; /* d (nu_h)_c / d x_r, tangential */
+                    for (a = 0; a < t.k; a++) gcr += ul[a][c] * gp[a * t.n + r];
+                    alpha2 += gcr * gcr;
+                }
+            for (c = 0; c <= t.n; c++) {
+                uh[c] = 0.0;
+                for (a = 0; a < t.k; a++) uh[c] += ul[a][c] * phi[a];
+            }
+            wgt = t.qw[q] * mu * alpha2;
+            for (a = 0; a < t.k; a++) {
+                int64_t g = conn[(int64_t)a * T + e];
+                for (c = 0; c <= t.n; c++) acc[(int64_t)c * N + g] += wgt * uh[c] * phi[a];
+            }
+        }
+    }
+    for (i = 0; i < N * (t.n + 1); i++) f[i] = (double)acc[i];
+    free(acc);
+    return bad ? OR_EDEGENERATE : OR_OK;
+}

@@ -205,6 +205,41 @@ def test_config2_full_blocked_and_determinism(lf, c2):
     dm.close()
 
 
+def test_config2_every_value_written_each_launch(lf, c2):
+    """Every launch of the persistent blocked kernel (also after a schedule
+    rebuild by the autotuner, and with a coefficient) must write every value,
+    with the same bits."""
+    dm = lf.DeviceMesh.from_dict(c2)
+    cc = torch.as_tensor(c2["coef_c"], device="cuda")
+    ref = dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=lf.LFEM_SCATTER_BLOCKED)
+    refc = dm.assemble(lf.LFEM_MC, coef_c=cc, scatter=lf.LFEM_SCATTER_BLOCKED)
+    for rep in range(4):
+        if rep == 2:
+            lf.lfem_pattern_autotune(dm.handle, dm.pattern, lf.LFEM_M | lf.LFEM_A)
+        out = {k: torch.full((int(dm.nnz),), float("nan"), dtype=torch.float64, device="cuda") for k in ("M", "A")}
+        dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=lf.LFEM_SCATTER_BLOCKED, out=out)
+        outc = {"MC": torch.full((int(dm.nnz),), float("nan"), dtype=torch.float64, device="cuda")}
+        dm.assemble(lf.LFEM_MC, coef_c=cc, scatter=lf.LFEM_SCATTER_BLOCKED, out=outc)
+        for key in ("M", "A"):
+            assert torch.equal(out[key], ref[key]), (rep, key)
+        assert torch.equal(outc["MC"], refc["MC"]), rep
+    dm.close()
+
+
+@pytest.mark.parametrize("t", [t for t in meshgen.ALL_TYPES if t[1] <= 2])
+def test_small_every_value_written(lf, t):
+    """Small meshes (fewer blocks than workgroups; P1 meshes take the chunked
+    variant of the kernel) through the same block distribution."""
+    m = meshgen.small_mesh(*t, size=3)
+    dm = lf.DeviceMesh.from_dict(m)
+    dm.build_pattern()
+    for _ in range(3):
+        out = {k: torch.full((int(dm.nnz),), float("nan"), dtype=torch.float64, device="cuda") for k in ("M", "A")}
+        dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=lf.LFEM_SCATTER_BLOCKED, out=out)
+        assert bool(torch.isfinite(out["M"]).all()) and bool(torch.isfinite(out["A"]).all()), t
+    dm.close()
+
+
 def test_config2_atomic_close(lf, c2):
     dm = lf.DeviceMesh.from_dict(c2)
     a = dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=lf.LFEM_SCATTER_ATOMIC)
