@@ -223,6 +223,22 @@ lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double 
  */
 lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, void *stream);
 
+/*
+ * Non-linear terms of the paper's mean-curvature-flow example (section 6.2,
+ * the vector f = (f_1; f_2)): for a nodal vector field nu and a nodal scalar H,
+ *     alpha^2 = |grad_Gamma_h nu_h|^2   (Frobenius norm of the tangential
+ *               gradient of nu_h = sum_r nu_r phi_r),
+ *     f[c * N + j]     = sum_E sum_q w_q mu alpha^2 (nu_h)_c phi_j,  c < n_amb (f_1)
+ *     f[n_amb * N + j] = sum_E sum_q w_q mu alpha^2 H_h phi_j                  (f_2)
+ * nu: n_amb * N doubles, component-major (nu[c * N + r]); H: N doubles, or
+ * NULL for H = 1; f: (n_amb + 1) * N doubles, overwritten.  Any element type
+ * (in the bulk the gradient is the full gradient).  Deterministic like the
+ * load vector; uses the mesh's scratch buffer: calls on one mesh must not
+ * overlap.  Errors: LFEM_EINVAL (null mesh, nu or f with N > 0), LFEM_EHIP.
+ */
+lfem_status lfem_assemble_kll(lfem_mesh_t m, const double *nu, const double *H, double *f,
+                              void *stream);
+
 /* Number of degenerate (element, quadrature point) evaluations seen by this
  * mesh since creation or the last reset.  SYNCHRONISES the device. */
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate);

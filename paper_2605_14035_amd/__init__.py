@@ -29,7 +29,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -188,6 +188,12 @@ def lfem_assemble_load(mesh, coef_f, b, stream=None):
     st = _L.lfem_assemble_load(mesh, _ptr(coef_f, torch.float64, "coef_f"), _ptr(b, torch.float64, "b"),
                                _stream(stream))
     _lib.check(st, "lfem_assemble_load")
+
+
+def lfem_assemble_kll(mesh, nu, H, f, stream=None):
+    st = _L.lfem_assemble_kll(mesh, _ptr(nu, torch.float64, "nu"), _ptr(H, torch.float64, "H"),
+                              _ptr(f, torch.float64, "f"), _stream(stream))
+    _lib.check(st, "lfem_assemble_kll")
 
 
 def lfem_status_get(mesh) -> int:

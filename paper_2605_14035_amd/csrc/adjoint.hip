@@ -16,8 +16,13 @@
 // reproducible.
 //
 // The load vector b_j = sum_E sum_q w_q mu f_h(xi_q) phi_j(xi_q) (the
-// right-hand side of the paper's assembly, section 6.1) is staged and
-// gathered the same way.
+// right-hand side of the paper's assembly, section 6.1) and the non-linear
+// terms of the mean-curvature-flow example (section 6.2),
+//   f_1[c][j] = sum_E sum_q w mu alpha^2 (nu_h)_c phi_j,
+//   f_2[j]    = sum_E sum_q w mu alpha^2 H_h phi_j,
+//   alpha^2 = |grad_Gamma_h nu_h|^2 = sum_c g_c^T K g_c, g_c = sum_a nu_{c,a} grad_hat phi_a
+// (the Frobenius norm of the tangential gradient: |J K g|^2 = g^T K g), are
+// staged and gathered the same way.
 #include <cmath>
 
 #include "element.hpp"
@@ -182,6 +187,77 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ coords,
     for (int a = 0; a < E::k; ++a) out[a * T + e] = acc[a];
 }
 
+// per (local node a, channel c) non-linear load contributions into
+// out[(a*(n+1) + c)*T + e]: channels 0..n-1 the field components, n the
+// scalar H (NULL: H = 1)
+template <class E>
+__global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, const int32_t *__restrict__ conn,
+                                             const double *__restrict__ tab, int64_t N, int64_t T, int Q,
+                                             const double *__restrict__ nu, const double *__restrict__ Hs,
+                                             double *__restrict__ out, unsigned long long *__restrict__ degenerate)
+{
+    constexpr int NC = E::n + 1;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    int32_t nid[E::k];
+    double x[E::n][E::k], ul[NC][E::k], acc[NC][E::k];
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
+    gather_coords<E>(nid, coords, N, x);
+#pragma unroll
+    for (int a = 0; a < E::k; ++a) {
+#pragma unroll
+        for (int c = 0; c < E::n; ++c) ul[c][a] = nu[c * N + nid[a]];
+        ul[E::n][a] = Hs ? Hs[nid[a]] : 1.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c][a] = 0.0;
+    }
+    double J0[E::n][E::d], H[E::n][E::nh > 0 ? E::nh : 1];
+    jacobian_setup<E>(x, J0, H);
+    int bad = 0;
+    for (int q = 0; q < Q; ++q) {
+        cdouble *t = const_table(tab) + q * E::stride;
+        double J[E::n][E::d];
+        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        double K[E::d][E::d], mu;
+        geometry<E>(J, K, mu);
+        bad += !(mu > 0.0 && mu < INFINITY);
+        double alpha2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < E::n; ++c) {
+            double g[E::d];
+#pragma unroll
+            for (int m = 0; m < E::d; ++m) {
+                g[m] = 0.0;
+#pragma unroll
+                for (int a = 0; a < E::k; ++a) g[m] = fma(ul[c][a], t[E::off_g + a * E::d + m], g[m]);
+            }
+#pragma unroll
+            for (int m = 0; m < E::d; ++m) {
+                double kg = 0.0;
+#pragma unroll
+                for (int l = 0; l < E::d; ++l) kg = fma(K[m][l], g[l], kg);
+                alpha2 = fma(g[m], kg, alpha2);
+            }
+        }
+        const double wgt = t[0] * mu * alpha2;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double uh = 0.0;
+#pragma unroll
+            for (int a = 0; a < E::k; ++a) uh = fma(ul[c][a], t[E::off_phi + a], uh);
+            const double wu = wgt * uh;
+#pragma unroll
+            for (int a = 0; a < E::k; ++a) acc[c][a] = fma(wu, t[E::off_phi + a], acc[c][a]);
+        }
+    }
+    if (bad) atomicAdd(degenerate, static_cast<unsigned long long>(bad));
+#pragma unroll
+    for (int a = 0; a < E::k; ++a)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[(a * NC + c) * T + e] = acc[c][a];
+}
+
 // grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*n+c)*T + e]
 __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
                                                 const int32_t *__restrict__ ne_ptr,
@@ -191,7 +267,7 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
 {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= N) return;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // n <= 4 channels
     for (int32_t s = ne_ptr[r]; s < ne_ptr[r + 1]; ++s) {
         const int32_t inc = ne[s];
         const int64_t e = inc >> 4;
@@ -280,6 +356,30 @@ void dispatch_load(Mesh &m, const double *f, double *out, hipStream_t s)
     }
 }
 
+template <class E>
+void run_kll(Mesh &m, const double *nu, const double *H, double *out, hipStream_t s)
+{
+    if (m.T == 0) return;
+    k_kll<E><<<grid_for(m.T, 256), 256, 0, s>>>(m.coords, m.conn, m.tab, m.N, m.T, m.Q, nu, H, out,
+                                                m.degenerate);
+    LFEM_HIP(hipGetLastError());
+}
+
+void dispatch_kll(Mesh &m, const double *nu, const double *H, double *out, hipStream_t s)
+{
+    switch (m.etype) {
+    case S1P1: run_kll<ET<1, 1, 1>>(m, nu, H, out, s); break;
+    case S1P2: run_kll<ET<1, 1, 2>>(m, nu, H, out, s); break;
+    case S2P1: run_kll<ET<1, 2, 1>>(m, nu, H, out, s); break;
+    case S2P2: run_kll<ET<1, 2, 2>>(m, nu, H, out, s); break;
+    case B2P1: run_kll<ET<0, 2, 1>>(m, nu, H, out, s); break;
+    case B2P2: run_kll<ET<0, 2, 2>>(m, nu, H, out, s); break;
+    case B3P1: run_kll<ET<0, 3, 1>>(m, nu, H, out, s); break;
+    case B3P2: run_kll<ET<0, 3, 2>>(m, nu, H, out, s); break;
+    default: throw Error{LFEM_EUNSUPPORTED, "element type"};
+    }
+}
+
 }  // namespace
 
 double *mesh_scratch(Mesh &m, size_t bytes)
@@ -320,6 +420,18 @@ void launch_load(Mesh &m, const double *f, double *b, hipStream_t s)
     dispatch_load(m, f, stage, s);
     if (m.N > 0) {
         k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, 1, m.ne_ptr, m.ne, stage, b);
+        LFEM_HIP(hipGetLastError());
+    }
+}
+
+void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s)
+{
+    const int nc = m.namb + 1;
+    const size_t cnt = static_cast<size_t>(m.k) * nc * m.T;
+    double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
+    dispatch_kll(m, nu, H, stage, s);
+    if (m.N > 0) {
+        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, nc, m.ne_ptr, m.ne, stage, f);
         LFEM_HIP(hipGetLastError());
     }
 }

@@ -340,6 +340,14 @@ lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, v
     });
 }
 
+lfem_status lfem_assemble_kll(lfem_mesh_t m, const double *nu, const double *H, double *f, void *stream)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(m && ((nu && f) || m->N == 0), LFEM_EINVAL, "null mesh, nu or f");
+        launch_kll(*m, nu, H, f, S(stream));
+    });
+}
+
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate)
 {
     return guarded([&] {

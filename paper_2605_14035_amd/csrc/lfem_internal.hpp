@@ -196,5 +196,6 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
                        hipStream_t s);
 double *mesh_scratch(Mesh &m, size_t bytes);
 void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
+void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s);
 
 }  // namespace lfem

@@ -8,8 +8,8 @@ import numpy as np
 import torch
 
 from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFACE,
-               copy_from_device, lfem_assemble, lfem_assemble_load, lfem_energy, lfem_mesh_create,
-               lfem_mesh_destroy, lfem_mesh_set_coords, lfem_pattern_build,
+               copy_from_device, lfem_assemble, lfem_assemble_kll, lfem_assemble_load, lfem_energy,
+               lfem_mesh_create, lfem_mesh_destroy, lfem_mesh_set_coords, lfem_pattern_build,
                lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
 
 
@@ -87,6 +87,16 @@ class DeviceMesh:
         b = out if out is not None else torch.empty(self.N, dtype=torch.float64, device=self.coords.device)
         lfem_assemble_load(self.handle, f, b, stream)
         return b
+
+    def kll(self, nu, H=None, out=None, stream=None):
+        """Non-linear terms f = (f_1; f_2) of the mean-curvature-flow example as a
+        float64 (n_amb + 1, N) tensor; nu: (n_amb, N) nodal vector field, H: (N,)
+        or None for H = 1."""
+        n = self.coords.shape[0]
+        f = out if out is not None else torch.empty(n + 1, self.N, dtype=torch.float64,
+                                                    device=self.coords.device)
+        lfem_assemble_kll(self.handle, nu, H, f, stream)
+        return f
 
     def degenerate_count(self):
         return lfem_status_get(self.handle)
