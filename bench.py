@@ -123,6 +123,82 @@ def batched_vs_plain(lf, torch, meshgen, reps=5):
     return res
 
 
+def event_times(torch, fn, reps=20, warm=3):
+    """HIP-event durations (ms) of fn on the current stream: (min, mean)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = [a.elapsed_time(b) for a, b in ev]
+    return min(t), statistics.mean(t)
+
+
+def row_entry(name, ms, elements, alg_bytes, **extra):
+    tmin, tmean = ms
+    gbs = alg_bytes / (tmean * 1e-3) / 1e9
+    return {"what": name, "ms_min": tmin, "ms_mean": tmean, "elements": elements,
+            "elements_per_s": elements / (tmean * 1e-3), "alg_bytes": alg_bytes,
+            "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, **extra}
+
+
+def other_rows(lf, torch, meshgen, mesh2, dm2):
+    """The other calls of the boundary on their workloads (HIP-event timing of
+    the whole call, algorithmic bytes: every input read once, every output
+    written once)."""
+    import numpy as np
+    rows = {}
+    N, T = dm2.N, dm2.T
+    f = torch.as_tensor(mesh2["coef_c"], device="cuda")
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    rows["load_c2"] = row_entry("load vector b = int f_h phi_j, P2 ellipsoid (655,360 elements)",
+                                event_times(torch, lambda: lf.lfem_assemble_load(dm2.handle, f, b)), T,
+                                3 * N * 8 + 6 * T * 4 + N * 8 + N * 8)
+    X = mesh2["coords"]
+    g = X / np.array([1.0, 0.64, 0.36])[:, None]
+    nu = torch.as_tensor(g / np.linalg.norm(g, axis=0), device="cuda")
+    fk = torch.empty(4, N, dtype=torch.float64, device="cuda")
+    rows["kll_c2"] = row_entry("mean-curvature-flow non-linear terms f_1, f_2 (nu = nodal normals), P2 ellipsoid",
+                               event_times(torch, lambda: lf.lfem_assemble_kll(dm2.handle, nu, f, fk)), T,
+                               3 * N * 8 + 6 * T * 4 + 3 * N * 8 + N * 8 + 4 * N * 8)
+    m5 = meshgen.config5()
+    dm5 = lf.DeviceMesh.from_dict(m5)
+    u = torch.as_tensor(m5["u"], device="cuda")
+    v = torch.as_tensor(m5["v"], device="cuda")
+    gr = torch.empty(3, dm5.N, dtype=torch.float64, device="cuda")
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    N5, T5 = dm5.N, dm5.T
+    rows["shape_grad_c5"] = row_entry(
+        "shape gradient of u^T A(x) u + v^T M(x) v, P2 displaced sphere (163,840 elements)",
+        event_times(torch, lambda: lf.lfem_shape_grad(dm5.handle, u, u, 1.0, v, v, 1.0, gr)), T5,
+        3 * N5 * 8 + 6 * T5 * 4 + 2 * N5 * 8 + 3 * N5 * 8)
+    rows["energy_c5"] = row_entry(
+        "matrix-free J(x) = u^T A(x) u + v^T M(x) v, same mesh",
+        event_times(torch, lambda: lf.lfem_energy(dm5.handle, u, u, 1.0, v, v, 1.0, J)), T5,
+        3 * N5 * 8 + 6 * T5 * 4 + 2 * N5 * 8 + 8)
+    dm5.close()
+    m3 = meshgen.config3()
+    dm3 = lf.DeviceMesh.from_dict(m3)
+    dm3.build_pattern()
+    ca = torch.as_tensor(m3["coef_a"], device="cuda")
+    scatter = lf.lfem_pattern_autotune(dm3.handle, dm3.pattern, lf.LFEM_M | lf.LFEM_A)
+    o3 = {k: torch.empty(dm3.nnz, dtype=torch.float64, device="cuda") for k in ("M", "A")}
+    N3, T3, nnz3 = dm3.N, dm3.T, dm3.nnz
+    rows["tets_c3"] = row_entry(
+        "P2 tetrahedra M + A_a (a(x) nodal), unit cube 64^3 x 6 (1,572,864 elements), 11-point rule",
+        event_times(torch, lambda: lf.lfem_assemble(dm3.handle, dm3.pattern, lf.LFEM_M | lf.LFEM_A, ca, None,
+                                                    o3["M"], o3["A"], None, scatter), reps=5, warm=1),
+        T3, 3 * N3 * 8 + 10 * T3 * 4 + N3 * 8 + 2 * nnz3 * 8,
+        scatter={1: "blocked", 2: "staged", 3: "atomic"}.get(scatter, str(scatter)), nnz=nnz3)
+    dm3.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +207,8 @@ def main():
     ap.add_argument("--scatter", default="blocked", choices=["blocked", "staged", "atomic"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the load / non-linear terms / shape gradient / tetrahedra measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 256 MiB device copy 3 times (a kernel of known traffic that "
                          "calibrates hardware byte counters)")
@@ -229,6 +307,9 @@ def main():
         },
         "pattern_build_s": pattern_s,
     }
+    if not args.no_rows:
+        print("[bench] other rows (load, non-linear terms, shape gradient, tetrahedra)", file=sys.stderr, flush=True)
+        result["rows"] = other_rows(lf, torch, meshgen, mesh, dm)
     dm.close()
     if not args.no_batch:
         print("[bench] batched vs plain (256 meshes)", file=sys.stderr, flush=True)

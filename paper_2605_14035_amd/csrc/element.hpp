@@ -155,19 +155,22 @@ __device__ __forceinline__ void geometry(const double (&J)[E::n][E::d], double (
                                          double &mu)
 {
     if constexpr (E::surf && E::d == 1) {
+        // one reciprocal square root gives both: mu = g / sqrt(g), 1/g = (1/sqrt(g))^2
         const double g = fma(J[0][0], J[0][0], J[1][0] * J[1][0]);
-        mu = sqrt(g);
-        K[0][0] = 1.0 / g;
+        const double rr = rsqrt(g);
+        mu = g * rr;
+        K[0][0] = rr * rr;
     } else if constexpr (E::surf && E::d == 2) {
         const double nx = fma(J[1][0], J[2][1], -(J[2][0] * J[1][1]));
         const double ny = fma(J[2][0], J[0][1], -(J[0][0] * J[2][1]));
         const double nz = fma(J[0][0], J[1][1], -(J[1][0] * J[0][1]));
         const double det = fma(nx, nx, fma(ny, ny, nz * nz));  // det G = |t1 x t2|^2
-        mu = sqrt(det);
+        const double rr = rsqrt(det);  // mu = det / sqrt(det), 1/det = rr^2
+        mu = det * rr;
         const double g11 = fma(J[0][0], J[0][0], fma(J[1][0], J[1][0], J[2][0] * J[2][0]));
         const double g12 = fma(J[0][0], J[0][1], fma(J[1][0], J[1][1], J[2][0] * J[2][1]));
         const double g22 = fma(J[0][1], J[0][1], fma(J[1][1], J[1][1], J[2][1] * J[2][1]));
-        const double inv = 1.0 / det;
+        const double inv = rr * rr;
         K[0][0] = g22 * inv;
         K[0][1] = -g12 * inv;
         K[1][0] = K[0][1];
