@@ -182,6 +182,28 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
         event_times(torch, lambda: lf.lfem_energy(dm5.handle, u, u, 1.0, v, v, 1.0, J)), T5,
         3 * N5 * 8 + 6 * T5 * 4 + 2 * N5 * 8 + 8)
     dm5.close()
+    # one step of Dziuk's mean-curvature-flow scheme (M, A, S = M + tau A, rhs = M x) on a P2
+    # sphere of the size of the paper's finest MCF meshes, eager and replayed from a HIP graph
+    from meshgen import meshes as mg
+    Vs, Fs = mg.sphere_nvb(9, order=2)
+    cs, ks = mg.to_soa(Vs, Fs)
+    dms = lf.DeviceMesh.from_dict(dict(domain="surface", dim=2, order=2, quad=6, coords=cs, conn=ks))
+    so = dms.dziuk_system(1e-3)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dms.dziuk_system(1e-3, out=so)
+    Ns, Ts, nnzs = dms.N, dms.T, dms.nnz
+    # assembly: coordinates and connectivity in, M and A out; row pass: M, A, pattern, x in, S, rhs out
+    bstep = (3 * Ns * 8 + 6 * Ts * 4 + 2 * nnzs * 8) + (2 * nnzs * 8 + (Ns + 1) * 4 + nnzs * 4 + 3 * Ns * 8
+                                                      + nnzs * 8 + 3 * Ns * 8)
+    rows["dziuk_step_eager"] = row_entry(
+        f"Dziuk MCF step (M, A, S = M + tau A, rhs = M x), P2 sphere ({Ts} elements), one call",
+        event_times(torch, lambda: dms.dziuk_system(1e-3, out=so)), Ts, bstep)
+    rows["dziuk_step_graph"] = row_entry(
+        f"the same step replayed from a captured HIP graph", event_times(torch, graph.replay), Ts, bstep)
+    del graph
+    dms.close()
     m3 = meshgen.config3()
     dm3 = lf.DeviceMesh.from_dict(m3)
     dm3.build_pattern()

@@ -164,6 +164,24 @@ lfem_status lfem_assemble_weighted(lfem_mesh_t m, lfem_pattern_t p, const double
                                    double *vals, void *stream);
 
 /*
+ * Per-step system of the linearly implicit mean-curvature-flow scheme the
+ * paper times against DUNE (section 6.3, Dziuk's algorithm):
+ *     (M(x^n) + tau A(x^n)) x^{n+1} = M(x^n) x^n.
+ * Assembles M and A at the mesh's current coordinates into vals_m, vals_a
+ * (nnz doubles each, the pattern's tuned scatter variant), then forms
+ * vals_s = vals_m + tau * vals_a and rhs[c * N + i] = sum_j M_ij x[c * N + j]
+ * for c < n_amb (each row summed in column order: deterministic).  x: n_amb *
+ * N doubles, component-major, or NULL for the mesh's own coordinates.  The
+ * linear solve is the caller's.  After one call (which builds the pattern's
+ * lazy structures) a call allocates nothing, so it can be captured in a HIP
+ * graph and replayed while the coordinates change in place.
+ * Errors: LFEM_EINVAL (handles, null buffers, non-finite tau), LFEM_EHIP.
+ */
+lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const double *x,
+                              double *vals_m, double *vals_a, double *vals_s, double *rhs,
+                              void *stream);
+
+/*
  * Autotune the scatter variant and row-block size of pattern p for the
  * matrix set `what` by timing the candidates on stream (SYNCHRONISES).
  * The choice is kept in the pattern and used by LFEM_SCATTER_AUTO.

@@ -1,5 +1,6 @@
 // The extern "C" boundary of liblfem.so: argument checks, handle lifetime and
 // error translation.  No exception crosses this file's functions.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -250,6 +251,20 @@ lfem_status lfem_assemble(lfem_mesh_t m, lfem_pattern_t p, unsigned what, const 
         o.vals_a = vals_a;
         o.vals_mc = vals_mc;
         launch_numeric(*m, *p, o, variant, S(stream));
+    });
+}
+
+lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const double *x,
+                              double *vals_m, double *vals_a, double *vals_s, double *rhs, void *stream)
+{
+    return guarded([&] {
+        check_numeric_args(m, p, LFEM_M | LFEM_A, nullptr, vals_m, vals_a, nullptr);
+        LFEM_REQUIRE(vals_s || p->nnz == 0, LFEM_EINVAL, "vals_s is null");
+        LFEM_REQUIRE(rhs || m->N == 0, LFEM_EINVAL, "rhs is null");
+        LFEM_REQUIRE(std::isfinite(tau), LFEM_EINVAL, "tau is not finite");
+        int variant = p->tuned_variant;
+        if (variant == LFEM_SCATTER_BLOCKED && p->sched.nb == 0 && m->T > 0) variant = LFEM_SCATTER_STAGED;
+        launch_dziuk(*m, *p, tau, x, vals_m, vals_a, vals_s, rhs, variant, S(stream));
     });
 }
 

@@ -197,5 +197,7 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
 double *mesh_scratch(Mesh &m, size_t bytes);
 void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
 void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s);
+void launch_dziuk(Mesh &m, Pattern &p, double tau, const double *x, double *vals_m, double *vals_a,
+                  double *vals_s, double *rhs, int variant, hipStream_t s);
 
 }  // namespace lfem

@@ -8,8 +8,9 @@ import numpy as np
 import torch
 
 from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFACE,
-               copy_from_device, lfem_assemble, lfem_assemble_kll, lfem_assemble_load, lfem_energy,
-               lfem_mesh_create, lfem_mesh_destroy, lfem_mesh_set_coords, lfem_pattern_build,
+               copy_from_device, lfem_assemble, lfem_assemble_kll, lfem_assemble_load,
+               lfem_dziuk_system, lfem_energy, lfem_mesh_create, lfem_mesh_destroy,
+               lfem_mesh_set_coords, lfem_pattern_build,
                lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
 
 
@@ -97,6 +98,21 @@ class DeviceMesh:
                                                     device=self.coords.device)
         lfem_assemble_kll(self.handle, nu, H, f, stream)
         return f
+
+    def dziuk_system(self, tau, x=None, out=None, stream=None):
+        """Per-step system of Dziuk's mean-curvature-flow scheme at the current
+        coordinates: dict with "M", "A", "S" = M + tau A (nnz,) and "rhs" = M x
+        as an (n_amb, N) tensor (x: (n_amb, N) or None for the coordinates)."""
+        self.build_pattern(stream)
+        out = dict(out or {})
+        dev = self.coords.device
+        for key in ("M", "A", "S"):
+            if key not in out:
+                out[key] = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        if "rhs" not in out:
+            out["rhs"] = torch.empty(self.coords.shape[0], self.N, dtype=torch.float64, device=dev)
+        lfem_dziuk_system(self.handle, self.pattern, tau, x, out["M"], out["A"], out["S"], out["rhs"], stream)
+        return out
 
     def degenerate_count(self):
         return lfem_status_get(self.handle)
