@@ -12,7 +12,7 @@
 //
 // Scatter variants:
 //   atomic  - FP64 atomics into zeroed values (order not fixed)
-//   staged  - local matrices written structure-of-arrays, then one thread per
+//   staged  - local matrices written element by element, then one thread per
 //             CSR slot sums its contribution list in ascending element order
 //   blocked - one workgroup owns a contiguous block of rows whose values live
 //             in LDS; it recomputes every element touching the block and
