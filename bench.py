@@ -73,7 +73,19 @@ def cpu_baseline(mesh):
     T = mesh["conn"].shape[1]
     return {"value": T / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"whole workload ({T} elements, M and A, COO + stable sort + CSR), "
-                      f"median of 3 runs: {t:.2f} s"}
+                      f"median of 3 runs: {t:.2f} s",
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def batched_vs_plain(lf, torch, meshgen, reps=5):
@@ -217,6 +229,13 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
                                                     o3["M"], o3["A"], None, scatter), reps=5, warm=1),
         T3, 3 * N3 * 8 + 10 * T3 * 4 + N3 * 8 + 2 * nnz3 * 8,
         scatter={1: "blocked", 2: "staged", 3: "atomic"}.get(scatter, str(scatter)), nnz=nnz3)
+    # FP64 flops per element of the local matrices: per point the Jacobian (10 nodes x 9 entries
+    # FMA), cofactors, determinant and K = C^T C / det^2 (~120), the coefficient (10 FMA), then
+    # per pair (55) one mass and six stiffness FMAs; 2 flops per FMA
+    flops_e = 11 * (2 * 90 + 120 + 2 * 10 + 55 * 2 * 7)
+    t3 = rows["tets_c3"]["ms_mean"] * 1e-3
+    rows["tets_c3"].update({"flops_per_element": flops_e, "tflops": flops_e * T3 / t3 / 1e12,
+                            "frac_fp64_peak": flops_e * T3 / t3 / 78.6e12})
     dm3.close()
     return rows
 
@@ -291,6 +310,22 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     kern_ms = statistics.mean(ev_ms)
+    ev_sorted = sorted(ev_ms)
+    kern_p90 = ev_sorted[min(len(ev_sorted) - 1, int(0.9 * len(ev_sorted)))]
+    # the 241 MB of values nearly fit the 256 MB last-level cache: time the
+    # same launch with a 512 MB read-modify-write scrub between launches too
+    scrub = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    scrubbed = []
+    for _ in range(20):
+        scrub.mul_(1.0)
+        a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_ev.record(stream)
+        step()
+        b_ev.record(stream)
+        torch.cuda.synchronize()
+        scrubbed.append(a_ev.elapsed_time(b_ev))
+    del scrub
+    scrub_ms = statistics.median(scrubbed)
     ms_per_step = wall * 1e3 / args.steps
     value = T / (ms_per_step * 1e-3)
 
@@ -325,6 +360,9 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": KERNEL_NAME, "alg_bytes_per_launch": b_alg,
             "kernel_ms_mean": kern_ms, "kernel_ms_min": min(ev_ms),
+            "kernel_ms_median": statistics.median(ev_ms), "kernel_ms_p90": kern_p90,
+            "kernel_ms_median_after_512MB_scrub": scrub_ms,
+            "frac_after_512MB_scrub": b_alg / (scrub_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "kernel_source_digest": digest,
         },
         "pattern_build_s": pattern_s,
