@@ -224,6 +224,48 @@ def p1_to_p2(V, F, edges):
 
 
 # --------------------------------------------------------------------------
+# P1 -> P3, P4 (segments and triangles)
+# --------------------------------------------------------------------------
+def p1_to_pp(V, F, p, edges):
+    """Lattice nodes of order p (3 or 4) on straight segments / triangles.
+
+    Local order: vertices; then for each local edge (u, v) of ``edges`` its
+    p - 1 nodes from u to v (barycentric position (p - i, i) / p on the
+    edge, i = 1..p-1); then interior triangle nodes, p = 3: (1,1,1)/3,
+    p = 4: (2,1,1)/4, (1,2,1)/4, (1,1,2)/4.  Nodes on an edge are created
+    once per distinct edge, from its lower to its higher vertex id, and each
+    element takes them in its own direction."""
+    nV, T = len(V), len(F)
+    keys = np.concatenate([_edge_keys(F[:, i], F[:, j], nV) for (i, j) in edges])
+    uniq, inv = np.unique(keys, return_inverse=True)
+    lo, hi = uniq // nV, uniq % nV
+    ne = len(uniq)
+    # node i (1..p-1) of distinct edge g sits at (p - i, i) / p from lo to hi
+    newV = [V]
+    for i in range(1, p):
+        newV.append(((p - i) * V[lo] + i * V[hi]) / p)
+    cols = [F]
+    for s_, (u, v) in enumerate(edges):
+        g = inv[s_ * T:(s_ + 1) * T]
+        forward = F[:, u] < F[:, v]
+        for i in range(1, p):
+            idx = np.where(forward, i, p - i)       # position counted from lo
+            cols.append((nV + (idx - 1) * ne + g)[:, None])
+    out_V = np.concatenate(newV)
+    if F.shape[1] == 3:
+        base = len(out_V)
+        A, B, C = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+        if p == 3:
+            interior = [(A + B + C) / 3.0]
+        else:
+            interior = [(2 * A + B + C) / 4.0, (A + 2 * B + C) / 4.0, (A + B + 2 * C) / 4.0]
+        for n_i, P in enumerate(interior):
+            cols.append((base + n_i * T + np.arange(T))[:, None])
+        out_V = np.concatenate([out_V] + interior)
+    return out_V, np.concatenate(cols, 1)
+
+
+# --------------------------------------------------------------------------
 # locality ordering (space-filling curve)
 # --------------------------------------------------------------------------
 def _spread3(x: np.ndarray) -> np.ndarray:

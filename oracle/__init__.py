@@ -116,7 +116,9 @@ def _check(st, what):
 def basis(d: int, p: int, xi):
     """Values (k,) and reference gradients (k, d) of the nodal basis at xi."""
     xi = np.ascontiguousarray(np.atleast_1d(xi), dtype=np.float64)
-    k = (d + 1) if p == 1 else (d + 1) * (d + 2) // 2
+    k = lib().oracle_nodes_per_element(d, p)
+    if k < 0:
+        raise ValueError(f"no nodal basis of order {p} in dimension {d}")
     phi = np.zeros(k)
     dphi = np.zeros((k, d))
     _check(lib().oracle_basis(d, p, _ptr(xi, C.c_double), _ptr(phi, C.c_double),

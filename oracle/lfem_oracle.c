@@ -56,7 +56,7 @@ typedef double real;
 #define OR_ENOMEM 2
 #define OR_EDEGENERATE 3
 
-#define KMAX 10
+#define KMAX 15
 #define DMAX 3
 
 /* ---------------------------------------------------------------------- */
@@ -70,7 +70,76 @@ int oracle_nodes_per_element(int d, int p)
 {
     if (p == 1) return d + 1;
     if (p == 2) return (d + 1) * (d + 2) / 2;
+    if ((p == 3 || p == 4) && d == 1) return p + 1;
+    if ((p == 3 || p == 4) && d == 2) return (p + 1) * (p + 2) / 2;
     return -1;
+}
+
+/* Orders 3 and 4 on segments and triangles (the paper's dimension analysis,
+ * section 6.4, runs p = 1..4).  Node a has the multi-index alpha (|alpha| = p)
+ * of its barycentric position alpha / p, in the order: vertices; then for each
+ * edge (u -> v) of the edge list its p - 1 nodes from u to v (alpha_u = p - i,
+ * alpha_v = i, i = 1..p-1); then the interior nodes (p = 3: (1,1,1); p = 4:
+ * (2,1,1), (1,2,1), (1,1,2)).  The Lagrange function of node alpha is
+ *   phi_alpha = prod_j prod_{m < alpha_j} (p lambda_j - m) / (m + 1),
+ * which is 1 at its node and 0 at every other node of the lattice. */
+static void node_alpha(int d, int p, int a, int *alpha)
+{
+    int j, nv = d + 1;
+    for (j = 0; j <= d; j++) alpha[j] = 0;
+    if (a < nv) {
+        alpha[a] = p;
+        return;
+    }
+    a -= nv;
+    {
+        int ne = (d == 1) ? 1 : 3;
+        const int(*E)[2] = (d == 1) ? SEG_E : TRI_E;
+        if (a < ne * (p - 1)) {
+            int e = a / (p - 1), i = a % (p - 1) + 1;
+            alpha[E[e][0]] = p - i;
+            alpha[E[e][1]] = i;
+            return;
+        }
+        a -= ne * (p - 1);
+    }
+    /* interior (d == 2) */
+    alpha[0] = alpha[1] = alpha[2] = 1;
+    if (p == 4) alpha[a] = 2;
+}
+
+static void basis_lattice(int d, int p, const real *lam, const real (*dlam)[DMAX], real *phi,
+                          real *dphi)
+{
+    int k = oracle_nodes_per_element(d, p), a, j, m, r;
+    for (a = 0; a < k; a++) {
+        int alpha[DMAX + 1];
+        real f[DMAX + 1], df[DMAX + 1], val = 1.0;
+        node_alpha(d, p, a, alpha);
+        /* factor j and its derivative with respect to lambda_j */
+        for (j = 0; j <= d; j++) {
+            real fj = 1.0, dfj = 0.0;
+            for (r = 0; r < alpha[j]; r++) {
+                real t = (p * lam[j] - r) / (r + 1);
+                dfj = dfj * t + fj * (real)p / (r + 1);
+                fj *= t;
+            }
+            f[j] = fj;
+            df[j] = dfj;
+            val *= fj;
+        }
+        phi[a] = val;
+        for (m = 0; m < d; m++) {
+            real g = 0.0;
+            for (j = 0; j <= d; j++) {
+                real others = 1.0;
+                for (r = 0; r <= d; r++)
+                    if (r != j) others *= f[r];
+                g += df[j] * dlam[j][m] * others;
+            }
+            dphi[a * d + m] = g;
+        }
+    }
 }
 
 /* phi[a], dphi[a*d + m] = d phi_a / d xi_m at reference point xi[0..d-1] */
@@ -78,7 +147,7 @@ static int basis_r(int d, int p, const real *xi, real *phi, real *dphi)
 {
     real lam[DMAX + 1], dlam[DMAX + 1][DMAX];
     int i, m;
-    if (d < 1 || d > 3 || p < 1 || p > 2) return OR_EINVAL;
+    if (d < 1 || d > 3 || p < 1 || p > 4 || (p > 2 && d > 2)) return OR_EINVAL;
     lam[0] = 1.0;
     for (m = 0; m < d; m++) {
         lam[0] -= xi[m];
@@ -93,6 +162,10 @@ static int basis_r(int d, int p, const real *xi, real *phi, real *dphi)
             phi[i] = lam[i];
             for (m = 0; m < d; m++) dphi[i * d + m] = dlam[i][m];
         }
+        return OR_OK;
+    }
+    if (p > 2) {
+        basis_lattice(d, p, lam, (const real(*)[DMAX])dlam, phi, dphi);
         return OR_OK;
     }
     /* p == 2: corners lambda (2 lambda - 1), then edges 4 lambda_i lambda_j */
@@ -118,7 +191,7 @@ int oracle_basis(int d, int p, const double *xi, double *phi, double *dphi)
 {
     real x[DMAX], f[KMAX], g[KMAX * DMAX];
     int i, st;
-    if (d < 1 || d > 3 || p < 1 || p > 2) return OR_EINVAL;
+    if (oracle_nodes_per_element(d, p) < 0 || d > 3) return OR_EINVAL;
     for (i = 0; i < d; i++) x[i] = xi[i];
     st = basis_r(d, p, x, f, g);
     for (i = 0; i < oracle_nodes_per_element(d, p); i++) phi[i] = (double)f[i];
@@ -232,7 +305,8 @@ static int point_geometry(const etype *t, const real *x /*[k][n]*/, int q, real 
 static int make_type(etype *t, int surface, int d, int p, int Q, const double *qp,
                      const double *qw)
 {
-    if (d < 1 || d > 3 || p < 1 || p > 2 || Q < 1) return OR_EINVAL;
+    if (d < 1 || d > 3 || p < 1 || p > 4 || Q < 1) return OR_EINVAL;
+    if (p > 2 && d > 2) return OR_EINVAL;
     if (surface && d == 3) return OR_EINVAL;
     if (!surface && d == 1) return OR_EINVAL;
     t->surface = surface;
