@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_adjoint(
     for (int q = 0; q < Q; ++q) {
         cdouble *t = const_table(tab) + q * E::stride;
         double J[E::n][E::d];
-        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        jacobian_q<E>(x, J0, H, t, J);
         double K[E::d][E::d], mu;
         geometry<E>(J, K, mu);
         bad += !(mu > 0.0 && mu < INFINITY);
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ coords,
     for (int q = 0; q < Q; ++q) {
         cdouble *t = const_table(tab) + q * E::stride;
         double J[E::n][E::d];
-        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        jacobian_q<E>(x, J0, H, t, J);
         double K[E::d][E::d], mu;
         geometry<E>(J, K, mu);  // K unused: only the measure is needed
         bad += !(mu > 0.0 && mu < INFINITY);
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, 
     for (int q = 0; q < Q; ++q) {
         cdouble *t = const_table(tab) + q * E::stride;
         double J[E::n][E::d];
-        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        jacobian_q<E>(x, J0, H, t, J);
         double K[E::d][E::d], mu;
         geometry<E>(J, K, mu);
         bad += !(mu > 0.0 && mu < INFINITY);
@@ -327,6 +327,12 @@ void dispatch(Mesh &m, bool grad, const double *u, const double *v, double alpha
     case S2P2: run_adj<ET<1, 2, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B2P1: run_adj<ET<0, 2, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B2P2: run_adj<ET<0, 2, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S1P3: run_adj<ET<1, 1, 3>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S1P4: run_adj<ET<1, 1, 4>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S2P3: run_adj<ET<1, 2, 3>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case S2P4: run_adj<ET<1, 2, 4>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B2P3: run_adj<ET<0, 2, 3>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B2P4: run_adj<ET<0, 2, 4>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B3P1: run_adj<ET<0, 3, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B3P2: run_adj<ET<0, 3, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
@@ -350,6 +356,12 @@ void dispatch_load(Mesh &m, const double *f, double *out, hipStream_t s)
     case S2P2: run_load<ET<1, 2, 2>>(m, f, out, s); break;
     case B2P1: run_load<ET<0, 2, 1>>(m, f, out, s); break;
     case B2P2: run_load<ET<0, 2, 2>>(m, f, out, s); break;
+    case S1P3: run_load<ET<1, 1, 3>>(m, f, out, s); break;
+    case S1P4: run_load<ET<1, 1, 4>>(m, f, out, s); break;
+    case S2P3: run_load<ET<1, 2, 3>>(m, f, out, s); break;
+    case S2P4: run_load<ET<1, 2, 4>>(m, f, out, s); break;
+    case B2P3: run_load<ET<0, 2, 3>>(m, f, out, s); break;
+    case B2P4: run_load<ET<0, 2, 4>>(m, f, out, s); break;
     case B3P1: run_load<ET<0, 3, 1>>(m, f, out, s); break;
     case B3P2: run_load<ET<0, 3, 2>>(m, f, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
@@ -374,6 +386,12 @@ void dispatch_kll(Mesh &m, const double *nu, const double *H, double *out, hipSt
     case S2P2: run_kll<ET<1, 2, 2>>(m, nu, H, out, s); break;
     case B2P1: run_kll<ET<0, 2, 1>>(m, nu, H, out, s); break;
     case B2P2: run_kll<ET<0, 2, 2>>(m, nu, H, out, s); break;
+    case S1P3: run_kll<ET<1, 1, 3>>(m, nu, H, out, s); break;
+    case S1P4: run_kll<ET<1, 1, 4>>(m, nu, H, out, s); break;
+    case S2P3: run_kll<ET<1, 2, 3>>(m, nu, H, out, s); break;
+    case S2P4: run_kll<ET<1, 2, 4>>(m, nu, H, out, s); break;
+    case B2P3: run_kll<ET<0, 2, 3>>(m, nu, H, out, s); break;
+    case B2P4: run_kll<ET<0, 2, 4>>(m, nu, H, out, s); break;
     case B3P1: run_kll<ET<0, 3, 1>>(m, nu, H, out, s); break;
     case B3P2: run_kll<ET<0, 3, 2>>(m, nu, H, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};

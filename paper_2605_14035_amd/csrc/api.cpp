@@ -120,7 +120,8 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
         LFEM_REQUIRE(out, LFEM_EINVAL, "out is null");
         *out = nullptr;
         const int et = etype_of(domain, dim, order);
-        LFEM_REQUIRE(order == 1 || order == 2, LFEM_EUNSUPPORTED, "order must be 1 or 2");
+        LFEM_REQUIRE(order >= 1 && order <= 4 && (order <= 2 || dim <= 2), LFEM_EUNSUPPORTED,
+                     "order must be 1 or 2 (3 and 4 on segments and triangles)");
         LFEM_REQUIRE(et >= 0, LFEM_EUNSUPPORTED, "unsupported (domain, dim)");
         LFEM_REQUIRE(n_nodes >= 0 && n_elems >= 0, LFEM_EINVAL, "negative size");
         LFEM_REQUIRE(n_nodes < (int64_t(1) << 31) - 1, LFEM_ERANGE, "n_nodes >= 2^31 - 1");
@@ -132,6 +133,8 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
         RefTable tab;
         LFEM_REQUIRE(build_ref_table(dim, order, quad_points, tab), LFEM_EUNSUPPORTED,
                      "no quadrature rule with that number of points for this simplex");
+        LFEM_REQUIRE(order <= 2 || tab.Q >= (dim == 1 ? 5 : 16), LFEM_EUNSUPPORTED,
+                     "orders 3 and 4 take the high-order rules (segment 5 or 6, triangle 16 points)");
         auto *m = new lfem_mesh_s();
         try {
             m->domain = domain;

@@ -50,9 +50,13 @@ struct ET {
     static constexpr int d = D;
     static constexpr int p = P;
     static constexpr int n = SURF ? D + 1 : D;
-    static constexpr int k = P == 1 ? D + 1 : (D + 1) * (D + 2) / 2;
+    static constexpr int k = D == 1 ? P + 1 : (D == 2 ? (P + 1) * (P + 2) / 2 : (P == 1 ? 4 : 10));
     static constexpr int np = k * (k + 1) / 2;
-    static constexpr int nh = P == 1 ? 0 : D * (D + 1) / 2;  // distinct Hessian slots (l <= m)
+    static constexpr int nh = P == 2 ? D * (D + 1) / 2 : 0;  // distinct Hessian slots (l <= m)
+    // orders 1 and 2: J(xi) = J0 + sum_l xi_l H_l with compile-time basis
+    // coefficients; orders 3 and 4 (segments, triangles): J(xi) from the
+    // tabulated reference gradients at the point
+    static constexpr bool affine_j = P <= 2;
     // per-quadrature-point table: [w, xi (d), phi (k), grad phi (k*d), phi_a phi_b (np)]
     static constexpr int off_xi = 1;
     static constexpr int off_phi = 1 + D;
@@ -64,7 +68,7 @@ struct ET {
     static constexpr int nsym = D * (D + 1) / 2;
     static constexpr int off_ra = off_pp + np;
     static constexpr int stride = 1 + D + k + k * D + np + np * nsym;
-    using B = RefBasis<D, P>;
+    using B = RefBasis<D, (P <= 2 ? P : 1)>;  // used only when affine_j
 };
 
 // Read-only tables are read through the constant address space: uniform loads
@@ -93,6 +97,7 @@ __device__ __forceinline__ void jacobian_setup(const double (&x)[E::n][E::k],
                                                double (&J0)[E::n][E::d],
                                                double (&H)[E::n][E::nh > 0 ? E::nh : 1])
 {
+    if constexpr (!E::affine_j) return;
 #pragma unroll
     for (int c = 0; c < E::n; ++c) {
 #pragma unroll
@@ -145,6 +150,28 @@ __device__ __forceinline__ void jacobian_at(const double (&J0)[E::n][E::d],
             }
             J[c][m] = acc;
         }
+}
+
+// J at quadrature point q whose table row is t: the affine form for orders 1
+// and 2, else sum_a x_a (grad_hat phi_a(xi_q))^T from the table
+template <class E>
+__device__ __forceinline__ void jacobian_q(const double (&x)[E::n][E::k], const double (&J0)[E::n][E::d],
+                                           const double (&H)[E::n][E::nh > 0 ? E::nh : 1], cdouble *t,
+                                           double (&J)[E::n][E::d])
+{
+    if constexpr (E::affine_j) {
+        jacobian_at<E>(J0, H, t + E::off_xi, J);
+    } else {
+#pragma unroll
+        for (int c = 0; c < E::n; ++c)
+#pragma unroll
+            for (int m = 0; m < E::d; ++m) {
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 0; a < E::k; ++a) acc = fma(x[c][a], t[E::off_g + a * E::d + m], acc);
+                J[c][m] = acc;
+            }
+    }
 }
 
 // K = G^{-1} and the measure from J (n x d).  Every fused multiply-add is

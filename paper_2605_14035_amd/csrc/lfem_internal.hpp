@@ -43,18 +43,38 @@ inline void dev_free(void *p)
 // ---------------------------------------------------------------------------
 // element types: (surface?, manifold dimension d, order p)
 // ---------------------------------------------------------------------------
-enum EType : int { S1P1 = 0, S1P2, S2P1, S2P2, B2P1, B2P2, B3P1, B3P2, NUM_ETYPES };
+// orders 3 and 4 (segments and triangles) follow the eight original types
+enum EType : int {
+    S1P1 = 0, S1P2, S2P1, S2P2, B2P1, B2P2, B3P1, B3P2,
+    S1P3, S1P4, S2P3, S2P4, B2P3, B2P4, NUM_ETYPES
+};
 
 inline int etype_of(int domain, int d, int p)
 {
-    if (domain == LFEM_SURFACE && d == 1) return p == 1 ? S1P1 : S1P2;
-    if (domain == LFEM_SURFACE && d == 2) return p == 1 ? S2P1 : S2P2;
-    if (domain == LFEM_BULK && d == 2) return p == 1 ? B2P1 : B2P2;
-    if (domain == LFEM_BULK && d == 3) return p == 1 ? B3P1 : B3P2;
+    if (p < 1 || p > 4 || (p > 2 && d > 2)) return -1;
+    if (p <= 2) {
+        if (domain == LFEM_SURFACE && d == 1) return p == 1 ? S1P1 : S1P2;
+        if (domain == LFEM_SURFACE && d == 2) return p == 1 ? S2P1 : S2P2;
+        if (domain == LFEM_BULK && d == 2) return p == 1 ? B2P1 : B2P2;
+        if (domain == LFEM_BULK && d == 3) return p == 1 ? B3P1 : B3P2;
+        return -1;
+    }
+    if (domain == LFEM_SURFACE && d == 1) return p == 3 ? S1P3 : S1P4;
+    if (domain == LFEM_SURFACE && d == 2) return p == 3 ? S2P3 : S2P4;
+    if (domain == LFEM_BULK && d == 2) return p == 3 ? B2P3 : B2P4;
     return -1;
 }
 
-inline int nodes_per_elem(int d, int p) { return p == 1 ? d + 1 : (d + 1) * (d + 2) / 2; }
+// largest element (quartic triangle) and the 32-bit words of its k x k
+// byte slot map
+constexpr int kMaxNodes = 15;
+constexpr int kMaxSlotWords = (kMaxNodes * kMaxNodes + 3) / 4;
+
+// nodes of the order-p Lagrange element: (p + d choose d)
+inline int nodes_per_elem(int d, int p)
+{
+    return d == 1 ? p + 1 : (d == 2 ? (p + 1) * (p + 2) / 2 : (p == 1 ? 4 : 10));
+}
 
 // Reference data per quadrature point q, `stride` doubles each:
 //   [0]                         weight w_q (weights sum to the reference measure)
@@ -144,7 +164,7 @@ struct Pattern {
     int max_row = 0;
     // staged scatter (built on first use)
     int32_t *cptr = nullptr;   // [nnz+1]
-    int32_t *clist = nullptr;  // [k*k*T] contributions e*128 + a*k + b, ascending per slot
+    int32_t *clist = nullptr;  // [k*k*T] contributions e*256 + a*k + b, ascending per slot
     double *stage = nullptr;
     size_t stage_bytes = 0;
     // blocked scatter

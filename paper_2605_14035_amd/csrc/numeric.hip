@@ -46,11 +46,17 @@ void launch_numeric(Mesh &m, Pattern &p, const NumericOut &no, int variant, hipS
 {
     switch (m.etype) {
     case S1P1:
-    case S1P2: numeric_curve(m, p, no, variant, s); break;
+    case S1P2:
+    case S1P3:
+    case S1P4: numeric_curve(m, p, no, variant, s); break;
     case S2P1:
-    case S2P2: numeric_surface(m, p, no, variant, s); break;
+    case S2P2:
+    case S2P3:
+    case S2P4: numeric_surface(m, p, no, variant, s); break;
     case B2P1:
-    case B2P2: numeric_planar(m, p, no, variant, s); break;
+    case B2P2:
+    case B2P3:
+    case B2P4: numeric_planar(m, p, no, variant, s); break;
     case B3P1:
     case B3P2: numeric_tet(m, p, no, variant, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};

@@ -157,8 +157,8 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
     const int32_t b = cptr[s], end = cptr[s + 1];
     for (int32_t c = b; c < end; ++c) {
         const int32_t code = clist[c];
-        const int64_t e = code >> 7;
-        const int ab = code & 127;
+        const int64_t e = code >> 8;
+        const int ab = code & 255;
         const int a = ab / K, bb = ab - a * K;
         const int p = pair_index<K>(a, bb);
 #pragma unroll
@@ -287,8 +287,10 @@ void with_rule(int Q, F &&fn)
 {
     constexpr int QA = E::d == 1 ? 2 : (E::d == 2 ? 3 : 4);
     constexpr int QB = E::d == 1 ? 3 : (E::d == 2 ? 6 : 11);
-    if (Q == QA) return fn(std::integral_constant<int, QA>{});
-    if (Q == QB) return fn(std::integral_constant<int, QB>{});
+    if constexpr (E::p <= 2) {  // orders 3 and 4 take only the high-order rules
+        if (Q == QA) return fn(std::integral_constant<int, QA>{});
+        if (Q == QB) return fn(std::integral_constant<int, QB>{});
+    }
     if constexpr (E::d == 1) {
         if (Q == 5) return fn(std::integral_constant<int, 5>{});
         if (Q == 6) return fn(std::integral_constant<int, 6>{});
@@ -346,17 +348,21 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         LFEM_HIP(hipGetLastError());
         return;
     }
-    // blocked
+    // blocked (block schedules exist for orders 1 and 2 only)
     LFEM_REQUIRE(p.sched.nb > 0, LFEM_EUNSUPPORTED, "pattern has no block schedule");
-    constexpr int NT = kSideThreads;
-    const bool side = p.sched.side_mode;
-    const size_t lds = side ? side_lds_bytes(NMAT, p.sched.cap, p.max_row) : block_lds_bytes(p, NMAT);
-    LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "block schedule exceeds LDS");
-    if (side) {
-        if constexpr (E::d <= 2) return launch_side<E, NM, HA, NT>(m, p, o, lds, s);
-        throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
+    if constexpr (E::p > 2) {
+        throw Error{LFEM_EUNSUPPORTED, "blocked scatter for orders above 2"};
+    } else {
+        constexpr int NT = kSideThreads;
+        const bool side = p.sched.side_mode;
+        const size_t lds = side ? side_lds_bytes(NMAT, p.sched.cap, p.max_row) : block_lds_bytes(p, NMAT);
+        LFEM_REQUIRE(lds <= 160 * 1024, LFEM_EUNSUPPORTED, "block schedule exceeds LDS");
+        if (side) {
+            if constexpr (E::d <= 2) return launch_side<E, NM, HA, NT>(m, p, o, lds, s);
+            throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
+        }
+        return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
     }
-    return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
 }
 
 // allow more than 64 KB of dynamic LDS for kern (once per size increase)

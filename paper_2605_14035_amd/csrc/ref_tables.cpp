@@ -22,7 +22,9 @@
 // Basis, in barycentric coordinates l_0 = 1 - sum xi, l_i = xi_i: P1 l_i;
 // P2 corners l_i (2 l_i - 1), edge nodes 4 l_i l_j with the edge order
 // segment (0,1); triangle (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2),
-// (0,2), (0,3), (1,3), (2,3).
+// (0,2), (0,3), (1,3), (2,3).  Orders 3 and 4 on segments and triangles (the
+// orders of the paper's dimension analysis, section 6.4): the lattice basis
+// described at eval_lattice below; they default to the high-order rules.
 #include <cmath>
 
 #include "lfem_internal.hpp"
@@ -172,6 +174,67 @@ const int EDGE_SEG[1][2] = {{0, 1}};
 const int EDGE_TRI[3][2] = {{0, 1}, {1, 2}, {2, 0}};
 const int EDGE_TET[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
 
+// Orders 3 and 4 (segments, triangles): node a is the lattice point alpha / p
+// (|alpha| = p), ordered vertices, then p - 1 nodes per edge (u, v) of the edge
+// list from u to v, then the interior nodes (p = 3: (1,1,1); p = 4: (2,1,1),
+// (1,2,1), (1,1,2)); its Lagrange function is
+//   phi_alpha(l) = prod_j prod_{r < alpha_j} (p l_j - r) / (r + 1).
+int lattice_nodes(int d, int p, int (*alpha)[3])
+{
+    int n = 0;
+    for (int i = 0; i <= d; ++i, ++n)
+        for (int j = 0; j <= d; ++j) alpha[n][j] = i == j ? p : 0;
+    const int ne = d == 1 ? 1 : 3;
+    const int(*E)[2] = d == 1 ? EDGE_SEG : EDGE_TRI;
+    for (int s = 0; s < ne; ++s)
+        for (int i = 1; i < p; ++i, ++n) {
+            for (int j = 0; j <= d; ++j) alpha[n][j] = 0;
+            alpha[n][E[s][0]] = p - i;
+            alpha[n][E[s][1]] = i;
+        }
+    if (d == 2) {
+        const int interior = p == 3 ? 1 : 3;
+        for (int c = 0; c < interior; ++c, ++n) {
+            alpha[n][0] = alpha[n][1] = alpha[n][2] = 1;
+            if (p == 4) alpha[n][c] = 2;
+        }
+    }
+    return n;
+}
+
+void eval_lattice(int d, int p, const double *l, const double (*dl)[3], double *phi, double *g)
+{
+    int alpha[15][3];
+    const int k = lattice_nodes(d, p, alpha);
+    for (int a = 0; a < k; ++a) {
+        double f[3], df[3];
+        for (int j = 0; j <= d; ++j) {
+            // f_j = prod_{r < alpha_j} (p l_j - r) / (r + 1) and its l_j-derivative
+            double v = 1.0, dv = 0.0;
+            for (int r = 0; r < alpha[a][j]; ++r) {
+                const double t = (p * l[j] - r) / (r + 1);
+                dv = dv * t + v * p / (r + 1);
+                v *= t;
+            }
+            f[j] = v;
+            df[j] = dv;
+        }
+        double val = 1.0;
+        for (int j = 0; j <= d; ++j) val *= f[j];
+        phi[a] = val;
+        for (int m = 0; m < d; ++m) {
+            double s = 0.0;
+            for (int j = 0; j <= d; ++j) {
+                double rest = df[j] * dl[j][m];
+                for (int i = 0; i <= d; ++i)
+                    if (i != j) rest *= f[i];
+                s += rest;
+            }
+            g[a * d + m] = s;
+        }
+    }
+}
+
 // values phi[k] and reference gradients g[k][d] at xi
 void eval_basis(int d, int p, const double *xi, double *phi, double *g)
 {
@@ -183,6 +246,10 @@ void eval_basis(int d, int p, const double *xi, double *phi, double *g)
         dl[0][m] = -1.0;
         l[m + 1] = xi[m];
         dl[m + 1][m] = 1.0;
+    }
+    if (p >= 3) {
+        eval_lattice(d, p, l, dl, phi, g);
+        return;
     }
     const int nc = d + 1;
     for (int i = 0; i < nc; ++i) {
@@ -209,8 +276,8 @@ void eval_basis(int d, int p, const double *xi, double *phi, double *g)
 
 int default_rule(int d, int p)
 {
-    if (d == 1) return p == 1 ? 2 : 3;
-    if (d == 2) return p == 1 ? 3 : 6;
+    if (d == 1) return p == 1 ? 2 : (p == 2 ? 3 : (p == 3 ? 5 : 6));
+    if (d == 2) return p == 1 ? 3 : (p == 2 ? 6 : 16);
     return p == 1 ? 4 : 11;
 }
 
@@ -228,7 +295,7 @@ bool build_ref_table(int d, int p, int npts, RefTable &out)
     out.data.assign(static_cast<size_t>(out.stride) * npts, 0.0);
     for (int q = 0; q < npts; ++q) {
         double *t = out.data.data() + static_cast<size_t>(q) * out.stride;
-        double phi[10], g[30];
+        double phi[15], g[45];
         eval_basis(d, p, r.pts[q].data(), phi, g);
         t[0] = r.w[q];
         for (int m = 0; m < d; ++m) t[1 + m] = r.pts[q][m];

@@ -144,7 +144,7 @@ __device__ __forceinline__ int side_qdata(const int32_t (&nid)[E::k], const doub
     for (int q = 0; q < Q; ++q) {
         cdouble *t = const_table(tab) + q * E::stride;
         double J[E::n][E::d];
-        jacobian_at<E>(J0, H, t + E::off_xi, J);
+        jacobian_q<E>(x, J0, H, t, J);
         double K[E::d][E::d], mu;
         geometry<E>(J, K, mu);
         bad += !(mu > 0.0 && mu < INFINITY);

@@ -211,7 +211,7 @@ __global__ void k_offsets(int k, int64_t T, const int32_t *__restrict__ conn,
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= T) return;
-    uint32_t words[25];
+    uint32_t words[kMaxSlotWords];  // kkp / 4 <= kMaxSlotWords (checked on the host)
     for (int w = 0; w < kkp / 4; ++w) words[w] = 0;
     for (int a = 0; a < k; ++a) {
         const int32_t row = conn[a * T + e];
@@ -264,7 +264,7 @@ __global__ void k_contrib_fill(int k, int64_t T, const int32_t *__restrict__ con
         for (int b = 0; b < k; ++b) {
             const int32_t slot = rb + off8[e * kkp + a * k + b];
             const int32_t pos = atomicAdd(&cursor[slot], 1);
-            clist[cptr[slot] + pos] = static_cast<int32_t>(e * 128 + a * k + b);
+            clist[cptr[slot] + pos] = static_cast<int32_t>(e * 256 + a * k + b);  // a*k + b < 256
         }
     }
 }
@@ -420,6 +420,8 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
         LFEM_HIP(hipGetLastError());
     }
     p.kkp = (m.k * m.k + 3) / 4 * 4;
+    LFEM_REQUIRE(m.k <= kMaxNodes && p.kkp / 4 <= kMaxSlotWords, LFEM_EUNSUPPORTED,
+                 "element has more nodes than the slot map holds");
     p.off8 = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * m.T);
     if (m.T > 0) {
         k_offsets<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.col_idx, p.off8,
@@ -453,8 +455,8 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
 void build_staged(Mesh &m, Pattern &p, hipStream_t s)
 {
     if (p.cptr) return;
-    LFEM_REQUIRE(m.T < (int64_t(1) << 24), LFEM_EUNSUPPORTED,
-                 "staged scatter supports at most 2^24 elements");
+    LFEM_REQUIRE(m.T < (int64_t(1) << 23), LFEM_EUNSUPPORTED,
+                 "staged scatter supports fewer than 2^23 elements");
     const int64_t kkT = static_cast<int64_t>(m.k) * m.k * m.T;
     int32_t *cnt = nullptr;
     int64_t *tot = nullptr;
@@ -515,6 +517,7 @@ void free_schedule(BlockSchedule &b)
 void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
 {
     LFEM_REQUIRE(max_rows >= 1 && max_rows <= kBlockMaxRows, LFEM_EINVAL, "rows per block out of range");
+    LFEM_REQUIRE(m.p <= 2, LFEM_EUNSUPPORTED, "block schedules cover orders 1 and 2");
     free_schedule(p.sched);
     BlockSchedule &b = p.sched;
     b.cap = cap;

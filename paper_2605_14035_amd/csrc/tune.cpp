@@ -90,7 +90,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
                 best_cap = cap;
             }
         }
-        if (m.T < (int64_t(1) << 24)) {
+        if (m.T < (int64_t(1) << 23)) {
             const float t = time_variant(m, p, o, LFEM_SCATTER_STAGED, s);
             if (verbose) std::fprintf(stderr, "[lfem tune] staged: %.1f us\n", t * 1e3);
             if (t < best) {

@@ -1,0 +1,130 @@
+"""GPU parity for cubic and quartic elements on curves, surfaces and planar
+triangles (the orders of the paper's dimension analysis, section 6.4): every
+output of the library against the oracle.  Orders 3 and 4 have no block
+schedule; the staged scatter is their deterministic default (a blocked
+request falls back to it) and the atomic one is checked beside it.
+
+Tolerances as for orders 1 and 2 (1e-12 row-scaled; atomic 1e-11; vectors
+1e-12 of their largest entry, the shape gradient 1e-11)."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_csr_close
+from meshgen import meshes as mg
+
+pytestmark = pytest.mark.gpu
+
+TYPES = [(dom, d, p) for (dom, d) in (("surface", 1), ("surface", 2), ("bulk", 2)) for p in (3, 4)]
+
+
+@pytest.fixture(scope="module")
+def lf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_14035_amd as lf
+    return lf
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def order_mesh(domain, d, p, seed=0):
+    """A small curved mesh of order p with random nodal coefficients."""
+    rng = np.random.default_rng(100 + 10 * d + p + seed)
+    if domain == "surface" and d == 1:
+        V, F = mg.circle(11)
+        V, F = mg.p1_to_pp(V, F, p, mg.SEG_EDGES)
+        V = mg.normalize_rows(V) * (1.0 + 0.05 * rng.uniform(-1, 1, size=len(V)))[:, None]
+        quad = 5 if p == 3 else 6
+    elif domain == "surface" and d == 2:
+        V, F = mg.icosphere_red(1)
+        V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
+        V = mg.normalize_rows(V) * (1.0 + 0.05 * rng.uniform(-1, 1, size=len(V)))[:, None]
+        quad = 16
+    else:
+        V, F = mg.square_tri(3)
+        V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
+        inter = np.all((V > 1e-12) & (V < 1 - 1e-12), axis=1)
+        V[inter] += rng.uniform(-0.02, 0.02, size=(int(inter.sum()), 2))
+        quad = 16
+    coords, conn = mg.to_soa(V, F)
+    N = coords.shape[1]
+    return dict(domain=domain, dim=d, order=p, quad=quad, coords=coords, conn=conn,
+                coef_a=rng.uniform(0.5, 2.0, size=N), coef_c=rng.uniform(0.5, 2.0, size=N))
+
+
+@pytest.mark.parametrize("t", TYPES)
+@pytest.mark.parametrize("variant", ["auto", "blocked", "staged", "atomic"])
+def test_matrices(lf, t, variant):
+    m = order_mesh(*t)
+    say("case", t, variant)
+    dm = lf.DeviceMesh.from_dict(m)
+    v = {"auto": lf.LFEM_SCATTER_AUTO, "blocked": lf.LFEM_SCATTER_BLOCKED,
+         "staged": lf.LFEM_SCATTER_STAGED, "atomic": lf.LFEM_SCATTER_ATOMIC}[variant]
+    ca = torch.as_tensor(m["coef_a"], device="cuda")
+    cc = torch.as_tensor(m["coef_c"], device="cuda")
+    out = dm.assemble(lf.LFEM_M | lf.LFEM_MC | lf.LFEM_A, coef_a=ca, coef_c=cc, scatter=v)
+    out2 = dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=v)
+    rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
+    tol = 1e-11 if variant == "atomic" else 1e-12
+    checks = [("M", out["M"], oracle.assemble(m, "mass")),
+              ("MC", out["MC"], oracle.assemble(m, "mass", coef=m["coef_c"])),
+              ("A_a", out["A"], oracle.assemble(m, "stiffness", coef=m["coef_a"])),
+              ("M2", out2["M"], oracle.assemble(m, "mass")),
+              ("A", out2["A"], oracle.assemble(m, "stiffness"))]
+    for name, got, ref in checks:
+        assert_csr_close(rp, ci, got.cpu().numpy(), ref, tol=tol, what=f"{t} {variant} {name}")
+    if variant != "atomic":
+        again = dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=v)
+        assert torch.equal(again["M"], out2["M"]) and torch.equal(again["A"], out2["A"])
+    info = lf.lfem_pattern_info(dm.pattern)
+    assert info["scatter"] == lf.LFEM_SCATTER_STAGED and info["blocks"] == 0
+    dm.close()
+
+
+@pytest.mark.parametrize("t", TYPES)
+def test_vectors(lf, t):
+    m = order_mesh(*t)
+    say("case", t, "load, terms, gradient")
+    dm = lf.DeviceMesh.from_dict(m)
+    n, N = m["coords"].shape
+    rng = np.random.default_rng(9)
+    f = m["coef_c"]
+    b = dm.load(torch.as_tensor(f, device="cuda")).cpu().numpy()
+    bref = oracle.load(m, f)
+    assert np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max()
+    nu, H = rng.normal(size=(n, N)), rng.normal(size=N)
+    fk = dm.kll(torch.as_tensor(nu, device="cuda"), torch.as_tensor(H, device="cuda")).cpu().numpy()
+    fref = oracle.kll(m, nu, H)
+    for c in range(n + 1):
+        assert np.abs(fk[c] - fref[c]).max() <= 1e-12 * np.abs(fref[c]).max(), c
+    u, w = rng.normal(size=N), rng.normal(size=N)
+    ut, wt = (torch.as_tensor(x, device="cuda") for x in (u, w))
+    g = torch.empty_like(dm.coords)
+    lf.lfem_shape_grad(dm.handle, ut, ut, 1.0, wt, wt, 0.5, g)
+    gref = oracle.shape_grad(m, u, u, 1.0, w, w, 0.5)
+    assert np.abs(g.cpu().numpy() - gref).max() <= 1e-11 * np.abs(gref).max()
+    dm.close()
+
+
+def test_rules_and_batch_limits(lf):
+    m = order_mesh("surface", 2, 3)
+    with pytest.raises(lf.LfemError) as e:
+        lf.DeviceMesh.from_dict(dict(m, quad=6))  # orders 3, 4 take the high-order rules
+    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    dm = lf.DeviceMesh.from_dict(dict(m, quad=0))  # default: the 16-point rule
+    dm.build_pattern()
+    with pytest.raises(lf.LfemError) as e:
+        lf.lfem_batch_create([dm.handle], [dm.pattern], lf.LFEM_M | lf.LFEM_A, 0)
+    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    out = dm.assemble(lf.LFEM_M)
+    rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
+    assert_csr_close(rp, ci, out["M"].cpu().numpy(), oracle.assemble(m, "mass"), what="default rule")
+    dm.close()
