@@ -198,6 +198,7 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     # sphere of the size of the paper's finest MCF meshes, eager and replayed from a HIP graph
     from meshgen import meshes as mg
     Vs, Fs = mg.sphere_nvb(9, order=2)
+    Vs, Fs, _ = mg.sfc_reorder(Vs, Fs)
     cs, ks = mg.to_soa(Vs, Fs)
     dms = lf.DeviceMesh.from_dict(dict(domain="surface", dim=2, order=2, quad=6, coords=cs, conn=ks))
     so = dms.dziuk_system(1e-3)
@@ -216,6 +217,29 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
         f"the same step replayed from a captured HIP graph", event_times(torch, graph.replay), Ts, bstep)
     del graph
     dms.close()
+    # the paper's dimension analysis (section 6.4): M + A on spheres of order p = 1..4 with about
+    # the same number of nodes, default rule and scatter of each order
+    for p_ord, (kind, r) in {1: ("red", 8), 2: ("nvb", 14), 3: ("nvb", 13), 4: ("nvb", 12)}.items():
+        V, F = mg.icosphere_red(r) if kind == "red" else mg.sphere_nvb(r)
+        if p_ord == 2:
+            V, F, _ = mg.p1_to_p2(V, F, mg.TRI_EDGES)
+        elif p_ord > 2:
+            V, F = mg.p1_to_pp(V, F, p_ord, mg.TRI_EDGES)
+        V = mg.normalize_rows(V)
+        V, F, _ = mg.sfc_reorder(V, F)  # locality order, as for the other workloads
+        cp, kp = mg.to_soa(V, F)
+        dmp = lf.DeviceMesh.from_dict(dict(domain="surface", dim=2, order=p_ord, quad=0, coords=cp, conn=kp))
+        dmp.build_pattern()
+        op = {k: torch.empty(dmp.nnz, dtype=torch.float64, device="cuda") for k in ("M", "A")}
+        Np, Tp, nnzp = dmp.N, dmp.T, dmp.nnz
+        ms = event_times(torch, lambda: lf.lfem_assemble(dmp.handle, dmp.pattern, lf.LFEM_M | lf.LFEM_A, None,
+                                                         None, op["M"], op["A"], None, lf.LFEM_SCATTER_AUTO))
+        info = lf.lfem_pattern_info(dmp.pattern)
+        rows[f"order{p_ord}_sphere"] = row_entry(
+            f"M + A on an order-{p_ord} sphere ({Tp} triangles, {Np} nodes)", ms, Tp,
+            3 * Np * 8 + kp.shape[0] * Tp * 4 + 2 * nnzp * 8, nodes=Np, nnz=nnzp,
+            nodes_per_s=Np / (ms[1] * 1e-3), scatter={1: "blocked", 2: "staged", 3: "atomic"}[info["scatter"]])
+        dmp.close()
     m3 = meshgen.config3()
     dm3 = lf.DeviceMesh.from_dict(m3)
     dm3.build_pattern()
@@ -368,7 +392,8 @@ def main():
         "pattern_build_s": pattern_s,
     }
     if not args.no_rows:
-        print("[bench] other rows (load, non-linear terms, shape gradient, tetrahedra)", file=sys.stderr, flush=True)
+        print("[bench] other rows (load, non-linear terms, shape gradient, Dziuk step, orders 1-4, tetrahedra)",
+              file=sys.stderr, flush=True)
         result["rows"] = other_rows(lf, torch, meshgen, mesh, dm)
     dm.close()
     if not args.no_batch:
