@@ -257,6 +257,21 @@ lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, v
 lfem_status lfem_assemble_kll(lfem_mesh_t m, const double *nu, const double *H, double *f,
                               void *stream);
 
+/*
+ * Host query of the reference data the library builds for an element type
+ * (no device is touched): the quadrature rule of quad_points points (0: the
+ * default of the type) and the nodal basis at its points, the precomputed
+ * quantities of the paper's assembly (section 5.2).  *q_out and *k_out get
+ * the number of points Q and of element nodes k; each non-NULL array gets
+ * w[Q] (weights, summing to the reference measure), xi[Q * dim] (points),
+ * phi[Q * k] (phi_a(xi_q) at q * k + a) and dphi[Q * k * dim]
+ * (d phi_a / d xi_m at (q * k + a) * dim + m).  Call with NULL arrays to
+ * learn the sizes.  Errors: LFEM_EINVAL (null q_out or k_out),
+ * LFEM_EUNSUPPORTED (type or rule).
+ */
+lfem_status lfem_reference_table(int dim, int order, int quad_points, int *q_out, int *k_out,
+                                 double *w, double *xi, double *phi, double *dphi);
+
 /* Number of degenerate (element, quadrature point) evaluations seen by this
  * mesh since creation or the last reset.  SYNCHRONISES the device. */
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate);

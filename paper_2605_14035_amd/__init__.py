@@ -29,7 +29,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -202,6 +202,22 @@ def lfem_assemble_kll(mesh, nu, H, f, stream=None):
     st = _L.lfem_assemble_kll(mesh, _ptr(nu, torch.float64, "nu"), _ptr(H, torch.float64, "H"),
                               _ptr(f, torch.float64, "f"), _stream(stream))
     _lib.check(st, "lfem_assemble_kll")
+
+
+def lfem_reference_table(dim: int, order: int, quad_points: int = 0) -> dict:
+    """Host query of the library's quadrature rule and nodal basis for an
+    element type: dict of numpy arrays w (Q,), xi (Q, dim), phi (Q, k),
+    dphi (Q, k, dim).  Touches no device."""
+    import numpy as np
+    q, k = C.c_int(), C.c_int()
+    _lib.check(_L.lfem_reference_table(dim, order, quad_points, C.byref(q), C.byref(k), None, None, None, None),
+               "lfem_reference_table")
+    out = {"w": np.zeros(q.value), "xi": np.zeros((q.value, dim)), "phi": np.zeros((q.value, k.value)),
+           "dphi": np.zeros((q.value, k.value, dim))}
+    ptrs = [C.c_void_p(out[key].ctypes.data) for key in ("w", "xi", "phi", "dphi")]
+    _lib.check(_L.lfem_reference_table(dim, order, quad_points, C.byref(q), C.byref(k), *ptrs),
+               "lfem_reference_table")
+    return out
 
 
 def lfem_status_get(mesh) -> int:

@@ -366,6 +366,33 @@ lfem_status lfem_assemble_kll(lfem_mesh_t m, const double *nu, const double *H, 
     });
 }
 
+lfem_status lfem_reference_table(int dim, int order, int quad_points, int *q_out, int *k_out,
+                                 double *w, double *xi, double *phi, double *dphi)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(q_out && k_out, LFEM_EINVAL, "null q_out or k_out");
+        LFEM_REQUIRE(dim >= 1 && dim <= 3 && order >= 1 && order <= 4 && (order <= 2 || dim <= 2),
+                     LFEM_EUNSUPPORTED, "no element of that dimension and order");
+        RefTable tab;
+        LFEM_REQUIRE(build_ref_table(dim, order, quad_points, tab), LFEM_EUNSUPPORTED,
+                     "no quadrature rule with that number of points for this simplex");
+        *q_out = tab.Q;
+        *k_out = tab.k;
+        const int d = dim, k = tab.k;
+        for (int q = 0; q < tab.Q; ++q) {
+            const double *t = tab.data.data() + static_cast<size_t>(q) * tab.stride;
+            if (w) w[q] = t[0];
+            for (int m = 0; m < d; ++m)
+                if (xi) xi[q * d + m] = t[1 + m];
+            for (int a = 0; a < k; ++a) {
+                if (phi) phi[q * k + a] = t[1 + d + a];
+                for (int m = 0; m < d; ++m)
+                    if (dphi) dphi[(q * k + a) * d + m] = t[1 + d + k + a * d + m];
+            }
+        }
+    });
+}
+
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate)
 {
     return guarded([&] {
