@@ -33,7 +33,7 @@ namespace lfem {
 namespace {
 
 // GRAD = false: per-element energy into out[e]
-// GRAD = true:  per (local node a, component c) contributions into out[(a*n+c)*T + e]
+// GRAD = true:  per (local node a, component c) contributions into out[(a*T + e)*n + c]
 template <class E, bool GRAD>
 __global__ __launch_bounds__(256) void k_adjoint(
     const double *__restrict__ coords, const int32_t *__restrict__ conn,
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_adjoint(
 #pragma unroll
         for (int a = 0; a < E::k; ++a)
 #pragma unroll
-            for (int c = 0; c < E::n; ++c) out[(a * E::n + c) * T + e] = acc[a][c];
+            for (int c = 0; c < E::n; ++c) out[(a * T + e) * E::n + c] = acc[a][c];
     }
 }
 
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ coords,
 }
 
 // per (local node a, channel c) non-linear load contributions into
-// out[(a*(n+1) + c)*T + e]: channels 0..n-1 the field components, n the
+// out[(a*T + e)*(n+1) + c]: channels 0..n-1 the field components, n the
 // scalar H (NULL: H = 1)
 template <class E>
 __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, const int32_t *__restrict__ conn,
@@ -255,10 +255,12 @@ __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, 
 #pragma unroll
     for (int a = 0; a < E::k; ++a)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[(a * NC + c) * T + e] = acc[c][a];
+        for (int c = 0; c < NC; ++c) out[(a * T + e) * NC + c] = acc[c][a];
 }
 
-// grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*n+c)*T + e]
+// grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*T + e)*n + c]
+// (one plane per local node, the n channels of a contribution side by side:
+// one cache line per incidence, coalesced writes by consecutive elements)
 __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
                                                 const int32_t *__restrict__ ne_ptr,
                                                 const int32_t *__restrict__ ne,
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
         const int32_t inc = ne[s];
         const int64_t e = inc >> 4;
         const int a = inc & 15;
-        for (int c = 0; c < n; ++c) acc[c] += stage[(a * n + c) * T + e];
+        for (int c = 0; c < n; ++c) acc[c] += stage[(a * T + e) * n + c];
     }
     for (int c = 0; c < n; ++c) grad[c * N + r] = acc[c];
 }
