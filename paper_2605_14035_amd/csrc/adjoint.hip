@@ -261,22 +261,59 @@ __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, 
 // grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*T + e)*n + c]
 // (one plane per local node, the n channels of a contribution side by side:
 // one cache line per incidence, coalesced writes by consecutive elements)
-__global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T, int n,
+template <int NCH>
+__global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T,
                                                 const int32_t *__restrict__ ne_ptr,
                                                 const int32_t *__restrict__ ne,
                                                 const double *__restrict__ stage,
                                                 double *__restrict__ grad)
 {
+    constexpr int U = 8;  // incidences in flight per thread
     const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= N) return;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // n <= 4 channels
-    for (int32_t s = ne_ptr[r]; s < ne_ptr[r + 1]; ++s) {
-        const int32_t inc = ne[s];
-        const int64_t e = inc >> 4;
-        const int a = inc & 15;
-        for (int c = 0; c < n; ++c) acc[c] += stage[(a * T + e) * n + c];
+    double acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+    const int32_t b1 = ne_ptr[r + 1];
+    for (int32_t s0 = ne_ptr[r]; s0 < b1; s0 += U) {
+        const int cnt = min(U, b1 - s0);
+        int32_t inc[U];
+        double v[U][NCH];
+#pragma unroll
+        for (int i = 0; i < U; ++i) inc[i] = i < cnt ? ne[s0 + i] : 0;
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+            if (i < cnt) {
+                const int64_t e = inc[i] >> 4;
+                const int a = inc[i] & 15;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) v[i][c] = stage[(a * T + e) * NCH + c];
+            }
+        // added in ascending incidence order, as without the batching
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+            if (i < cnt) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) acc[c] += v[i][c];
+            }
     }
-    for (int c = 0; c < n; ++c) grad[c * N + r] = acc[c];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) grad[c * N + r] = acc[c];
+}
+
+void gather(int64_t N, int64_t T, int n, const int32_t *ne_ptr, const int32_t *ne, const double *stage,
+            double *out, hipStream_t s)
+{
+    if (N == 0) return;
+    const unsigned grid = static_cast<unsigned>((N + 255) / 256);
+    switch (n) {
+    case 1: k_gather<1><<<grid, 256, 0, s>>>(N, T, ne_ptr, ne, stage, out); break;
+    case 2: k_gather<2><<<grid, 256, 0, s>>>(N, T, ne_ptr, ne, stage, out); break;
+    case 3: k_gather<3><<<grid, 256, 0, s>>>(N, T, ne_ptr, ne, stage, out); break;
+    case 4: k_gather<4><<<grid, 256, 0, s>>>(N, T, ne_ptr, ne, stage, out); break;
+    default: throw Error{LFEM_EINVAL, "gather channels"};
+    }
+    LFEM_HIP(hipGetLastError());
 }
 
 constexpr int RED_NT = 256;
@@ -438,10 +475,7 @@ void launch_load(Mesh &m, const double *f, double *b, hipStream_t s)
     const size_t cnt = static_cast<size_t>(m.k) * m.T;
     double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
     dispatch_load(m, f, stage, s);
-    if (m.N > 0) {
-        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, 1, m.ne_ptr, m.ne, stage, b);
-        LFEM_HIP(hipGetLastError());
-    }
+    gather(m.N, m.T, 1, m.ne_ptr, m.ne, stage, b, s);
 }
 
 void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s)
@@ -450,10 +484,7 @@ void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream
     const size_t cnt = static_cast<size_t>(m.k) * nc * m.T;
     double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
     dispatch_kll(m, nu, H, stage, s);
-    if (m.N > 0) {
-        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, nc, m.ne_ptr, m.ne, stage, f);
-        LFEM_HIP(hipGetLastError());
-    }
+    gather(m.N, m.T, nc, m.ne_ptr, m.ne, stage, f, s);
 }
 
 void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
@@ -463,10 +494,7 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
     const size_t cnt = static_cast<size_t>(m.k) * m.namb * m.T;
     double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
     dispatch(m, true, u, v, alpha, w, z, beta, stage, s);
-    if (m.N > 0) {
-        k_gather<<<grid_for(m.N, 256), 256, 0, s>>>(m.N, m.T, m.namb, m.ne_ptr, m.ne, stage, grad);
-        LFEM_HIP(hipGetLastError());
-    }
+    gather(m.N, m.T, m.namb, m.ne_ptr, m.ne, stage, grad, s);
 }
 
 }  // namespace lfem
