@@ -154,15 +154,31 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
     double acc[NMAT];
 #pragma unroll
     for (int mat = 0; mat < NMAT; ++mat) acc[mat] = 0.0;
-    const int32_t b = cptr[s], end = cptr[s + 1];
-    for (int32_t c = b; c < end; ++c) {
-        const int32_t code = clist[c];
-        const int64_t e = code >> 8;
-        const int ab = code & 255;
-        const int a = ab / K, bb = ab - a * K;
-        const int p = pair_index<K>(a, bb);
+    // up to U contributions in flight, added in ascending element order
+    constexpr int U = 8;
+    const int32_t end = cptr[s + 1];
+    for (int32_t c0 = cptr[s]; c0 < end; c0 += U) {
+        const int cnt = min(U, end - c0);
+        int32_t code[U];
+        double v[U][NMAT];
 #pragma unroll
-        for (int mat = 0; mat < NMAT; ++mat) acc[mat] += stage[(e * NP + p) * NMAT + mat];
+        for (int i = 0; i < U; ++i) code[i] = i < cnt ? clist[c0 + i] : 0;
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+            if (i < cnt) {
+                const int64_t e = code[i] >> 8;
+                const int ab = code[i] & 255;
+                const int a = ab / K, bb = ab - a * K;
+                const int p = pair_index<K>(a, bb);
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = stage[(e * NP + p) * NMAT + mat];
+            }
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+            if (i < cnt) {
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) acc[mat] += v[i][mat];
+            }
     }
     double *outs[3] = {v0, v1, v2};
 #pragma unroll
