@@ -374,7 +374,19 @@ __device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nlo
     for (int mat = 0; mat < NMAT; ++mat) {
         double *__restrict__ out = g.v[mat] + base;
         double *reg = lds + mat * rs;
-        for (int i = threadIdx.x; i < nloc; i += NT) {
+        // eight LDS reads in flight per thread before their stores
+        int i = threadIdx.x;
+        for (; i + 7 * NT < nloc; i += 8 * NT) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = reg[i + u * NT];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                out[i + u * NT] = t[u];
+                reg[i + u * NT] = 0.0;
+            }
+        }
+        for (; i < nloc; i += NT) {
             out[i] = reg[i];
             reg[i] = 0.0;
         }
