@@ -5,7 +5,8 @@
  * What it computes.  For a mesh of linear (P1) or quadratic (P2)
  * isoparametric simplices -- curves in R^2, surfaces in R^3, bulk domains in
  * R^2 and R^3 (the element types of the paper's table of supported elements,
- * section 5) -- it assembles in FP64:
+ * section 5) -- and of orders 3 and 4 on segments and triangles (the orders
+ * of its dimension analysis, section 6.4) it assembles in FP64:
  *
  *   mass              M_ij   = sum_E sum_q w_q mu_E(xi_q) phi_i phi_j
  *   stiffness         A_ij   = sum_E sum_q w_q mu_E(xi_q) grad phi_i . grad phi_j
@@ -29,6 +30,9 @@
  *    local node a of element e (the paper's element array E), corners first
  *    in anticlockwise order, then edge nodes: segment (0,1); triangle
  *    (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2), (0,2), (0,3), (1,3), (2,3).
+ *    Orders 3 and 4: the p - 1 nodes of each edge from its first corner to
+ *    its second, then the interior nodes (order 3: the centroid; order 4:
+ *    (2,1,1)/4, (1,2,1)/4, (1,1,2)/4 in barycentric coordinates).
  *  - Every array argument is a DEVICE pointer owned by the caller; the
  *    library never frees it.  A mesh keeps the coords / conn pointers it was
  *    given (no copy): they must stay valid, and conn unchanged, for the
@@ -81,7 +85,8 @@ typedef struct lfem_batch_s *lfem_batch_t;
 
 /*
  * Create a mesh handle.  domain: LFEM_SURFACE or LFEM_BULK; dim: manifold
- * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1 or 2.  The ambient
+ * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1 or 2, or 3 or 4 for
+ * d <= 2 (these take the high-order rules and the staged scatter).  The ambient
  * dimension is n_amb = d + 1 (surface) or d (bulk), so coords has
  * n_amb * n_nodes entries and conn has k * n_elems entries, k = C(order+d, d).
  * quad_points selects the quadrature rule on the reference simplex by its
@@ -95,6 +100,8 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * high-order rules of its precomputations (section 5.2: Gauss of degree 10 or
  * more on segments, Dunavant of degree 8 on triangles), with the weights
  * summing to the reference measure.  Batched assembly takes the two default rules only.
+ * Orders 3 and 4 take only the high-order rules (defaults: segment 5 points
+ * for order 3 and 6 for order 4; triangle 16).
  * Builds the node -> element
  * incidence on the device (asynchronous on stream).
  * Errors: LFEM_EINVAL (sizes, nulls, n_elems * k >= 2^31),

@@ -1,5 +1,5 @@
 // Numeric phase of tetrahedral domains: the kernels of numeric_impl.hpp instantiated
-// for P1 and P2 (one translation unit per element family, built in parallel).
+// for orders 1 and 2 (one translation unit per element family, built in parallel).
 #include "numeric_impl.hpp"
 
 namespace lfem {

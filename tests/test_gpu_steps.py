@@ -111,3 +111,16 @@ def test_mean_curvature_flow_shrinks_sphere(lf):
     assert abs(r.mean() - exact) < 3e-3
     assert r.max() - r.min() < 1e-2  # stays round
     dm.close()
+
+
+def test_empty_mesh_and_bad_tau(lf):
+    m = dict(meshgen.small_mesh("surface", 2, 2, size=2))
+    m["conn"] = np.zeros((6, 0), dtype=np.int32)
+    dm = lf.DeviceMesh.from_dict(m)
+    out = dm.dziuk_system(0.01)
+    torch.cuda.synchronize()
+    assert bool((out["rhs"] == 0).all())
+    with pytest.raises(lf.LfemError) as e:
+        dm.dziuk_system(float("nan"))
+    assert e.value.status == lf.LFEM_EINVAL
+    dm.close()
