@@ -151,6 +151,13 @@ def event_times(torch, fn, reps=20, warm=3):
     return min(t), statistics.mean(t)
 
 
+def dd_bytes(d, domain, N, T, nnz):
+    """Algorithmic bytes of an M + A assembly: coordinates, connectivity, two value arrays."""
+    n_amb = d + 1 if domain == "surface" else d
+    k = (d + 1) * (d + 2) // 2
+    return n_amb * N * 8 + k * T * 4 + 2 * nnz * 8
+
+
 def row_entry(name, ms, elements, alg_bytes, **extra):
     tmin, tmean = ms
     gbs = alg_bytes / (tmean * 1e-3) / 1e9
@@ -217,8 +224,8 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
         f"the same step replayed from a captured HIP graph", event_times(torch, graph.replay), Ts, bstep)
     del graph
     dms.close()
-    # the paper's dimension analysis (section 6.4): M + A on spheres of order p = 1..4 with about
-    # the same number of nodes, default rule and scatter of each order
+    # order sweep: M + A on spheres of order p = 1..4 with about the same number of nodes, default
+    # rule and scatter of each order
     for p_ord, (kind, r) in {1: ("red", 8), 2: ("nvb", 14), 3: ("nvb", 13), 4: ("nvb", 12)}.items():
         V, F = mg.icosphere_red(r) if kind == "red" else mg.sphere_nvb(r)
         if p_ord == 2:
@@ -240,6 +247,31 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
             3 * Np * 8 + kp.shape[0] * Tp * 4 + 2 * nnzp * 8, nodes=Np, nnz=nnzp,
             nodes_per_s=Np / (ms[1] * 1e-3), scatter={1: "blocked", 2: "staged", 3: "atomic"}[info["scatter"]])
         dmp.close()
+    # the paper's dimension analysis (section 6.4) compares P2 codes across dimensions, surface and
+    # bulk: M + A for a P2 curve, sphere, square and cube at about 400k elements each (autotuned)
+    dim_meshes = {
+        "curve": ("surface", 1, lambda: mg.circle(393216, order=2)),
+        "sphere": ("surface", 2, lambda: mg.sphere_nvb(14, order=2)),
+        "square": ("bulk", 2, lambda: mg.square_tri(453, order=2)),
+        "cube": ("bulk", 3, lambda: mg.kuhn_cube(40, order=2)[:2]),
+    }
+    for name, (dom, dd, make) in dim_meshes.items():
+        V, F = make()
+        V, F, _ = mg.sfc_reorder(V, F)
+        cd, kd = mg.to_soa(V, F)
+        dmd = lf.DeviceMesh.from_dict(dict(domain=dom, dim=dd, order=2, quad=0, coords=cd, conn=kd))
+        dmd.build_pattern()
+        variant = lf.lfem_pattern_autotune(dmd.handle, dmd.pattern, lf.LFEM_M | lf.LFEM_A)
+        od = {k: torch.empty(dmd.nnz, dtype=torch.float64, device="cuda") for k in ("M", "A")}
+        Nd, Td, nnzd = dmd.N, dmd.T, dmd.nnz
+        ms = event_times(torch, lambda: lf.lfem_assemble(dmd.handle, dmd.pattern, lf.LFEM_M | lf.LFEM_A, None,
+                                                         None, od["M"], od["A"], None, lf.LFEM_SCATTER_AUTO),
+                         reps=10, warm=2)
+        rows[f"p2_{name}"] = row_entry(
+            f"P2 M + A, {dom} d={dd} ({name}, {Td} elements, {Nd} nodes)", ms, Td,
+            dd_bytes(dd, dom, Nd, Td, nnzd), nodes=Nd, nnz=nnzd, ns_per_element=ms[1] * 1e6 / Td,
+            scatter={1: "blocked", 2: "staged", 3: "atomic"}[variant])
+        dmd.close()
     m3 = meshgen.config3()
     dm3 = lf.DeviceMesh.from_dict(m3)
     dm3.build_pattern()

@@ -5,8 +5,9 @@
  * What it computes.  For a mesh of linear (P1) or quadratic (P2)
  * isoparametric simplices -- curves in R^2, surfaces in R^3, bulk domains in
  * R^2 and R^3 (the element types of the paper's table of supported elements,
- * section 5) -- and of orders 3 and 4 on segments and triangles (the orders
- * of its dimension analysis, section 6.4) it assembles in FP64:
+ * section 5) -- and of orders 3 and 4 on segments and triangles (the paper
+ * notes its assembly extends to degree 3 and up, section 1, and its mesh
+ * utility builds orders 2 to 4, section 5.4) -- it assembles in FP64:
  *
  *   mass              M_ij   = sum_E sum_q w_q mu_E(xi_q) phi_i phi_j
  *   stiffness         A_ij   = sum_E sum_q w_q mu_E(xi_q) grad phi_i . grad phi_j

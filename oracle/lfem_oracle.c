@@ -75,8 +75,9 @@ int oracle_nodes_per_element(int d, int p)
     return -1;
 }
 
-/* Orders 3 and 4 on segments and triangles (the paper's dimension analysis,
- * section 6.4, runs p = 1..4).  Node a has the multi-index alpha (|alpha| = p)
+/* Orders 3 and 4 on segments and triangles (the paper notes that its assembly
+ * extends to degree 3 and up, section 1; its mesh utility builds orders 2 to
+ * 4, section 5.4).  Node a has the multi-index alpha (|alpha| = p)
  * of its barycentric position alpha / p, in the order: vertices; then for each
  * edge (u -> v) of the edge list its p - 1 nodes from u to v (alpha_u = p - i,
  * alpha_v = i, i = 1..p-1); then the interior nodes (p = 3: (1,1,1); p = 4:

@@ -23,8 +23,9 @@
 // P2 corners l_i (2 l_i - 1), edge nodes 4 l_i l_j with the edge order
 // segment (0,1); triangle (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2),
 // (0,2), (0,3), (1,3), (2,3).  Orders 3 and 4 on segments and triangles (the
-// orders of the paper's dimension analysis, section 6.4): the lattice basis
-// described at eval_lattice below; they default to the high-order rules.
+// paper notes that its assembly extends to degree 3 and up, section 1, and its
+// mesh utility builds orders 2 to 4, section 5.4): the lattice basis described
+// at eval_lattice below; they default to the high-order rules.
 #include <cmath>
 
 #include "lfem_internal.hpp"

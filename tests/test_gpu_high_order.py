@@ -1,5 +1,6 @@
 """GPU parity for cubic and quartic elements on curves, surfaces and planar
-triangles (the orders of the paper's dimension analysis, section 6.4): every
+triangles (degree 3 and up, which the paper notes its assembly extends to,
+section 1; its mesh utility builds orders 2 to 4, section 5.4): every
 output of the library against the oracle.  Orders 3 and 4 have no block
 schedule; the staged scatter is their deterministic default (a blocked
 request falls back to it) and the atomic one is checked beside it.

@@ -1,5 +1,6 @@
 """Pins of the oracle's cubic and quartic elements on segments and triangles
-(the orders of the paper's dimension analysis, section 6.4).
+(degree 3 and up, which the paper notes its assembly extends to, section 1;
+its mesh utility builds orders 2 to 4, section 5.4).
 
 * the nodal basis against an independent construction: the Lagrange basis of
   the node lattice obtained by solving the Vandermonde system of the
