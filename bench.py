@@ -380,8 +380,20 @@ def main():
         b_ev.record(stream)
         torch.cuda.synchronize()
         scrubbed.append(a_ev.elapsed_time(b_ev))
-    del scrub
     scrub_ms = statistics.median(scrubbed)
+    # practical ceiling: a plain device copy of 256 MiB (read + write), median of 10
+    dst = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    src = scrub[:dst.numel()]
+    copies = []
+    for _ in range(10):
+        a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_ev.record(stream)
+        dst.copy_(src)
+        b_ev.record(stream)
+        torch.cuda.synchronize()
+        copies.append(a_ev.elapsed_time(b_ev))
+    copy_gbs = 2 * dst.numel() * 8 / (statistics.median(copies) * 1e-3) / 1e9
+    del scrub, dst, src
     ms_per_step = wall * 1e3 / args.steps
     value = T / (ms_per_step * 1e-3)
 
@@ -419,6 +431,7 @@ def main():
             "kernel_ms_median": statistics.median(ev_ms), "kernel_ms_p90": kern_p90,
             "kernel_ms_median_after_512MB_scrub": scrub_ms,
             "frac_after_512MB_scrub": b_alg / (scrub_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "copy_256MiB_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
             "kernel_source_digest": digest,
         },
         "pattern_build_s": pattern_s,
