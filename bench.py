@@ -71,9 +71,18 @@ def cpu_baseline(mesh):
         times.append(time.perf_counter() - t0)
     t = statistics.median(times)
     T = mesh["conn"].shape[1]
+    # numeric part alone: the local matrices of every element, no scatter
+    loc = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.element_matrices(mesh, "mass")
+        oracle.element_matrices(mesh, "stiffness")
+        loc.append(time.perf_counter() - t0)
+    tl = statistics.median(loc)
     return {"value": T / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"whole workload ({T} elements, M and A, COO + stable sort + CSR), "
                       f"median of 3 runs: {t:.2f} s",
+            "local_matrices_only_elements_per_s": T / tl,
             "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
 
 
