@@ -102,12 +102,29 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
 // each element's values together lets the values of one row share cache
 // lines (about 22 % faster on P2 tetrahedra than one plane per pair).
 // ---------------------------------------------------------------------------
+// pair table staged in LDS for orders 3 and 4 (tens of KB: more than the
+// scalar cache holds, so scalar loads would go to L2 for every pair)
+template <class E>
+constexpr bool stage_tab_lds() { return E::d <= 2 && E::p >= 3; }
+
+template <class E, int Q>
+constexpr size_t stage_lds_bytes() { return stage_tab_lds<E>() ? size_t(E::np) * Q * (1 + E::nsym) * sizeof(double) : 0; }
+
 template <class E, int Q, int NM, bool HA>
 __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
                                                double *__restrict__ stage)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= T) return;
+    constexpr bool TAB_LDS = stage_tab_lds<E>();
+    const double *tabp = g.tabp;
+    if constexpr (TAB_LDS) {
+        extern __shared__ double tab_lds[];
+        constexpr int n = E::np * Q * (1 + E::nsym);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tab_lds[i] = g.tabp[i];
+        __syncthreads();
+        tabp = tab_lds;
+    }
+    if (e >= T) return;  // after the only barrier
     constexpr int NMAT = NM + (HA ? 1 : 0);
     int32_t nid[E::k];
 #pragma unroll
@@ -133,7 +150,7 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
 #pragma unroll
         for (int p = 0; p < E::np; ++p) {
             double v[NMAT];
-            pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
+            pair_values<E, Q, NM, HA, TAB_LDS>(p, f, kq, tabp, v);
 #pragma unroll
             for (int mat = 0; mat < NMAT; ++mat) stage[(e * E::np + p) * NMAT + mat] = v[mat];
         }
@@ -356,7 +373,8 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         }
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
         with_rule<E>(m.Q, [&](auto qc) {
-            k_stage<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.stage);
+            constexpr int Q = decltype(qc)::value;
+            k_stage<E, Q, NM, HA><<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q>(), s>>>(g, m.T, m.conn, p.stage);
         });
         LFEM_HIP(hipGetLastError());
         k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, m.T, p.cptr, p.clist,

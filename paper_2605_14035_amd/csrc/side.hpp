@@ -38,6 +38,8 @@
 // the current block.
 #pragma once
 
+#include <type_traits>
+
 #include "blocked.hpp"
 
 namespace lfem {
@@ -219,7 +221,9 @@ __device__ __forceinline__ int32_t slot_off(const uint32_t (&ow)[KW], int a, int
 // data and the pair-major reference tensors.  Sums are split into
 // independent chains (mass: by point parity; stiffness: by slot of K) to
 // shorten the dependent FMA sequences.
-template <class E, int Q, int NM, bool HA>
+// TAB_LDS: tabp points to a copy of the pair table in LDS (high orders, whose
+// table outgrows the scalar cache); otherwise it is read with scalar loads.
+template <class E, int Q, int NM, bool HA, bool TAB_LDS = false>
 __device__ __forceinline__ void pair_values(int p, const double (&f)[NM > 0 ? NM : 1][Q],
                                             const double (&kq)[HA ? Q : 1][E::nsym],
                                             const double *__restrict__ tabp,
@@ -227,7 +231,10 @@ __device__ __forceinline__ void pair_values(int p, const double (&f)[NM > 0 ? NM
 {
     constexpr int PS = Q * (1 + E::nsym);
     constexpr int CA = E::nsym > 1 ? E::nsym : 3;  // stiffness chains
-    cdouble *t = const_table(tabp) + p * PS;
+    using TabPtr = std::conditional_t<TAB_LDS, const double *, cdouble *>;
+    TabPtr t;
+    if constexpr (TAB_LDS) t = tabp + p * PS;
+    else t = const_table(tabp) + p * PS;
 #pragma unroll
     for (int s = 0; s < NM; ++s) {
         double acc[2] = {0.0, 0.0};
