@@ -302,6 +302,22 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     rows["tets_c3"].update({"flops_per_element": flops_e, "tflops": flops_e * T3 / t3 / 1e12,
                             "frac_fp64_peak": flops_e * T3 / t3 / 78.6e12})
     dm3.close()
+    # the same workload under the degree-7 tetrahedral rule (35 points), the degree the paper
+    # integrates P2 tetrahedra with (section 5.2)
+    dm7 = lf.DeviceMesh.from_dict(dict(m3, quad=35))
+    dm7.build_pattern()
+    scatter7 = lf.lfem_pattern_autotune(dm7.handle, dm7.pattern, lf.LFEM_M | lf.LFEM_A)
+    rows["tets_c3_degree7"] = row_entry(
+        "P2 tetrahedra M + A_a, the same mesh and coefficient, 35-point degree-7 rule",
+        event_times(torch, lambda: lf.lfem_assemble(dm7.handle, dm7.pattern, lf.LFEM_M | lf.LFEM_A, ca, None,
+                                                    o3["M"], o3["A"], None, scatter7), reps=5, warm=1),
+        T3, 3 * N3 * 8 + 10 * T3 * 4 + N3 * 8 + 2 * nnz3 * 8,
+        scatter={1: "blocked", 2: "staged", 3: "atomic"}.get(scatter7, str(scatter7)), nnz=nnz3)
+    flops7 = 35 * (2 * 90 + 120 + 2 * 10 + 55 * 2 * 7)
+    t7 = rows["tets_c3_degree7"]["ms_mean"] * 1e-3
+    rows["tets_c3_degree7"].update({"flops_per_element": flops7, "tflops": flops7 * T3 / t7 / 1e12,
+                                    "frac_fp64_peak": flops7 * T3 / t7 / 78.6e12})
+    dm7.close()
     return rows
 
 

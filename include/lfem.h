@@ -96,11 +96,12 @@ typedef struct lfem_batch_s *lfem_batch_t;
  *            5, 6 (Gauss, degree 9, 11)
  *   triangle: 3 (interior orbit, degree 2, P1 default), 6 (degree 4, P2 default),
  *            16 (Dunavant, degree 8)
- *   tetrahedron: 4 (degree 2, P1 default), 11 (degree 4, P2 default)
+ *   tetrahedron: 4 (degree 2, P1 default), 11 (degree 4, P2 default),
+ *            35 (fully symmetric, degree 7, positive weights)
  * The rules are those of the paper's quadrature forms (section 3.2.2) and the
  * high-order rules of its precomputations (section 5.2: Gauss of degree 10 or
- * more on segments, Dunavant of degree 8 on triangles), with the weights
- * summing to the reference measure.  Batched assembly takes the two default rules only.
+ * more on segments, Dunavant of degree 8 on triangles, degree 7 on
+ * tetrahedra), with the weights summing to the reference measure.  Batched assembly takes the two default rules only.
  * Orders 3 and 4 take only the high-order rules (defaults: segment 5 points
  * for order 3 and 6 for order 4; triangle 16).
  * Builds the node -> element

@@ -29,7 +29,7 @@ mp.mp.dps = 40
 # rule id = (simplex dimension, number of points) -> polynomial degree
 DEGREE = {(1, 1): 1, (1, 2): 3, (1, 3): 5, (1, 4): 7, (1, 5): 9, (1, 6): 11,
           (2, 1): 1, (2, 3): 2, (2, 6): 4, (2, 16): 8,
-          (3, 1): 1, (3, 4): 2, (3, 11): 4}
+          (3, 1): 1, (3, 4): 2, (3, 11): 4, (3, 35): 7}
 
 
 def _bary_to_ref(lam):
@@ -65,6 +65,21 @@ def _orbit(sym, params):
                 lam[i] = a
                 lam[j] = a
                 pts.append(lam)
+        return pts
+    if sym == "S211":
+        a, b = params
+        c = 1 - 2 * a - b
+        pts = []
+        for i in range(4):
+            for j in range(i + 1, 4):
+                rest = [m for m in range(4) if m not in (i, j)]
+                for u, v in ((rest[0], rest[1]), (rest[1], rest[0])):
+                    lam = [None] * 4
+                    lam[i] = a
+                    lam[j] = a
+                    lam[u] = b
+                    lam[v] = c
+                    pts.append(lam)
         return pts
     raise ValueError(sym)
 
@@ -124,6 +139,63 @@ def _sym_moments_tet(lam):
 
 
 _TET_EXACT = [mp.mpf(1) / 6, mp.mpf(1) / 15, mp.mpf(1) / 30, mp.mpf(2) / 105, mp.mpf(1) / 210]
+
+
+# degree <= 7 invariants of the tetrahedron's symmetry group: with sum l = 1
+# every symmetric polynomial is a polynomial in e2, e3, e4 (elementary
+# symmetric polynomials of l0..l3); the monomials e2^a e3^b e4^c with
+# 2a + 3b + 4c <= 7 span degree <= 7
+_TET7 = [(a, b, c) for c in range(2) for b in range(3) for a in range(4) if 2 * a + 3 * b + 4 * c <= 7]
+
+
+def _elementary(lam, r):
+    from itertools import combinations
+    tot = mp.mpf(0)
+    for idx in combinations(range(len(lam)), r):
+        t = mp.mpf(1)
+        for i in idx:
+            t *= lam[i]
+        tot += t
+    return tot
+
+
+def _sym_moments_tet7(lam):
+    e2, e3, e4 = (_elementary(lam, r) for r in (2, 3, 4))
+    return [e2 ** a * e3 ** b * e4 ** c for a, b, c in _TET7]
+
+
+def _simplex_exact(factors, dim):
+    """int over the reference dim-simplex (measure 1/dim!) of the product of
+    polynomials in barycentric coordinates, each given as {exponents: coef}:
+    expanded into monomials, each integrated by the Dirichlet formula
+    prod a_i! / (sum a_i + dim)!."""
+    from fractions import Fraction
+    from math import factorial
+    poly = {(0,) * (dim + 1): Fraction(1)}
+    for f in factors:
+        out = {}
+        for ka, ca in poly.items():
+            for kb, cb in f.items():
+                k = tuple(x + y for x, y in zip(ka, kb))
+                out[k] = out.get(k, 0) + ca * cb
+        poly = out
+    tot = Fraction(0)
+    for k, c in poly.items():
+        num = 1
+        for x in k:
+            num *= factorial(x)
+        tot += c * Fraction(num, factorial(sum(k) + dim))
+    return mp.mpf(tot.numerator) / tot.denominator
+
+
+def _elementary_poly(r):
+    from fractions import Fraction
+    from itertools import combinations
+    return {tuple(1 if i in idx else 0 for i in range(4)): Fraction(1) for idx in combinations(range(4), r)}
+
+
+def _tet7_exact(a, b, c):
+    return _simplex_exact([_elementary_poly(2)] * a + [_elementary_poly(3)] * b + [_elementary_poly(4)] * c, 3)
 
 
 def _solve(orbits, moments, exact, x0):
@@ -217,6 +289,16 @@ def _rule_mp(dim: int, npts: int):
         if npts == 11:
             return _solve([("S4", 0), ("S31", 1), ("S22", 1)], _sym_moments_tet, _TET_EXACT,
                           [-0.013, 0.0076, 0.07, 0.025, 0.4])
+        if npts == 35:
+            # degree 7, the degree of the paper's tetrahedral rule (section
+            # 5.2): centroid + (a,a,a,1-3a) + (a,a,1/2-a,1/2-a) + two orbits
+            # (a,a,b,1-2a-b); eleven unknowns for the eleven invariants.  The
+            # start selects the root with positive weights and interior points
+            seed = [0.0159, 0.00705, 0.3157, 0.00532, 0.4495, 0.00135, 0.02127, 0.1466,
+                    0.0062, 0.1888, 0.04716]
+            exact = [_tet7_exact(a, b, c) for a, b, c in _TET7]
+            return _solve([("S4", 0), ("S31", 1), ("S22", 1), ("S211", 2), ("S211", 2)],
+                          _sym_moments_tet7, exact, seed)
     raise ValueError(f"no rule with {npts} points on the {dim}-simplex")
 
 

@@ -132,8 +132,9 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
     double x[E::n][E::k];
     gather_coords<E>(nid, g.coords, g.N, x);
     if constexpr (E::d == 3) {
-        // tetrahedra: the Q-point data of 11 points (77 doubles) outweighs the
-        // local matrices, so accumulate those point by point instead
+        // tetrahedra: the per-point data (7 doubles a point: 77 for 11 points,
+        // 245 for 35) outweighs the local matrices, so accumulate those point
+        // by point instead
         double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
         const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
         if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
@@ -308,7 +309,7 @@ Outs arrange(const NumericOut &o)
 
 // the rules of each element dimension as compile-time constants: the two
 // defaults (points: segment 2, 3; triangle 3, 6; tetrahedron 4, 11) and the
-// high-order ones (segment 5, 6; triangle 16)
+// high-order ones (segment 5, 6; triangle 16; tetrahedron 35)
 template <class E>
 constexpr bool high_order_rule(int Q)
 {
@@ -330,6 +331,9 @@ void with_rule(int Q, F &&fn)
     }
     if constexpr (E::d == 2) {
         if (Q == 16) return fn(std::integral_constant<int, 16>{});
+    }
+    if constexpr (E::d == 3) {
+        if (Q == 35) return fn(std::integral_constant<int, 35>{});
     }
     throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
 }

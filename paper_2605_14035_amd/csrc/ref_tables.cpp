@@ -19,6 +19,12 @@
 //                11 points, degree 4: centroid (-148/1875), orbit (1/14 x3, 11/14)
 //                (343/7500), orbit (a, a, 1/2-a, 1/2-a), a = (1 + sqrt(5/14))/4
 //                (56/375); volume-one weights, times 1/6
+//                35 points, degree 7 (the degree of the paper's tetrahedral rule,
+//                section 5.2): the centroid, one orbit (a,a,a,1-3a), one orbit
+//                (a,a,1/2-a,1/2-a) and two orbits of twelve (a,a,b,1-2a-b), all
+//                weights positive and all points inside; the eleven weights and
+//                parameters are the root of the moment equations described at
+//                solve_tet35, found by Newton's method from a six-digit start
 // Basis, in barycentric coordinates l_0 = 1 - sum xi, l_i = xi_i: P1 l_i;
 // P2 corners l_i (2 l_i - 1), edge nodes 4 l_i l_j with the edge order
 // segment (0,1); triangle (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2),
@@ -26,6 +32,8 @@
 // paper notes that its assembly extends to degree 3 and up, section 1, and its
 // mesh utility builds orders 2 to 4, section 5.4): the lattice basis described
 // at eval_lattice below; they default to the high-order rules.
+#include <algorithm>
+#include <array>
 #include <cmath>
 
 #include "lfem_internal.hpp"
@@ -88,6 +96,134 @@ void add_orbit111(Rule &r, double a, double b, double w)
     add_bary(r, {b, c, a}, w);
     add_bary(r, {c, a, b}, w);
     add_bary(r, {c, b, a}, w);
+}
+
+// Symmetric tetrahedral rule of degree 7 with 35 points.  Unknowns x: weights
+// and orbit parameters, in the order centroid (w), (a,a,a,1-3a) (w, a),
+// (a,a,1/2-a,1/2-a) (w, a), (a,a,b,1-2a-b) twice (w, a, b).  Equations: for
+// each exponent vector e = (e0 >= e1 >= e2 >= e3), |e| = 7 (eleven of them),
+// the full symmetrisation P_e(l) = sum over the 24 permutations s of
+// prod_i l_s(i)^e_i is integrated exactly; its exact integral over the
+// reference tetrahedron (volume 1/6) is 24 prod_i e_i! / 10!.  With
+// l0 + l1 + l2 + l3 = 1 the P_e span every symmetric polynomial of degree at
+// most 7, and a rule invariant under the permutations of the vertices that
+// integrates those exactly integrates every polynomial of degree 7 exactly.
+constexpr int kT35Orbits = 5;
+constexpr int kT35Size[kT35Orbits] = {1, 4, 6, 12, 12};
+constexpr int kT35Par[kT35Orbits] = {0, 1, 1, 2, 2};
+
+void t35_rep(int o, const double *par, double l[4])
+{
+    switch (o) {
+    case 0: l[0] = l[1] = l[2] = l[3] = 0.25; break;
+    case 1: l[0] = 1.0 - 3.0 * par[0]; l[1] = l[2] = l[3] = par[0]; break;
+    case 2: l[0] = l[1] = par[0]; l[2] = l[3] = 0.5 - par[0]; break;
+    default: l[0] = l[1] = par[0]; l[2] = par[1]; l[3] = 1.0 - 2.0 * par[0] - par[1]; break;
+    }
+}
+
+void t35_residual(const double *x, const int (*ex)[4], int ne, double *res)
+{
+    static const int perm[24][4] = {
+        {0, 1, 2, 3}, {0, 1, 3, 2}, {0, 2, 1, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {0, 3, 2, 1},
+        {1, 0, 2, 3}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 2, 3, 0}, {1, 3, 0, 2}, {1, 3, 2, 0},
+        {2, 0, 1, 3}, {2, 0, 3, 1}, {2, 1, 0, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {2, 3, 1, 0},
+        {3, 0, 1, 2}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 1, 2, 0}, {3, 2, 0, 1}, {3, 2, 1, 0}};
+    for (int i = 0; i < ne; ++i) {
+        double exact = 24.0;
+        for (int j = 0; j < 4; ++j)
+            for (int f = 2; f <= ex[i][j]; ++f) exact *= f;
+        for (int f = 2; f <= 10; ++f) exact /= f;
+        double sum = 0.0;
+        int at = 0;
+        for (int o = 0; o < kT35Orbits; ++o) {
+            const double w = x[at];
+            double l[4];
+            t35_rep(o, x + at + 1, l);
+            at += 1 + kT35Par[o];
+            double pe = 0.0;
+            for (const auto &s : perm) {
+                double t = 1.0;
+                for (int j = 0; j < 4; ++j)
+                    for (int c = 0; c < ex[i][j]; ++c) t *= l[s[j]];
+                pe += t;
+            }
+            sum += kT35Size[o] * w * pe;
+        }
+        res[i] = sum / exact - 1.0;
+    }
+}
+
+bool solve_tet35(Rule &r)
+{
+    constexpr int n = 11;
+    int ex[n][4], ne = 0;
+    for (int a = 7; a >= 0; --a)
+        for (int b = std::min(a, 7 - a); b >= 0; --b)
+            for (int c = std::min(b, 7 - a - b); c >= 0; --c) {
+                const int d = 7 - a - b - c;
+                if (d < 0 || d > c) continue;
+                if (ne == n) return false;
+                ex[ne][0] = a, ex[ne][1] = b, ex[ne][2] = c, ex[ne][3] = d;
+                ++ne;
+            }
+    if (ne != n) return false;
+    double x[n] = {0.0159142, 0.00705493, 0.315701, 0.00531615, 0.449510, 0.00135180,
+                   0.0212655, 0.146639,   0.00620119, 0.188834, 0.0471607};
+    double f[n], J[n][n + 1];
+    for (int it = 0; it < 8; ++it) {
+        t35_residual(x, ex, n, f);
+        for (int j = 0; j < n; ++j) {  // central differences
+            const double h = 1e-6 * std::max(std::fabs(x[j]), 1e-3);
+            double xp[n], xm[n], fp[n], fm[n];
+            std::copy(x, x + n, xp);
+            std::copy(x, x + n, xm);
+            xp[j] += h;
+            xm[j] -= h;
+            t35_residual(xp, ex, n, fp);
+            t35_residual(xm, ex, n, fm);
+            for (int i = 0; i < n; ++i) J[i][j] = (fp[i] - fm[i]) / (2.0 * h);
+        }
+        for (int i = 0; i < n; ++i) J[i][n] = -f[i];
+        for (int c = 0; c < n; ++c) {  // Gaussian elimination, partial pivoting
+            int piv = c;
+            for (int i = c + 1; i < n; ++i)
+                if (std::fabs(J[i][c]) > std::fabs(J[piv][c])) piv = i;
+            if (J[piv][c] == 0.0) return false;
+            for (int j = 0; j <= n; ++j) std::swap(J[c][j], J[piv][j]);
+            for (int i = c + 1; i < n; ++i) {
+                const double m = J[i][c] / J[c][c];
+                for (int j = c; j <= n; ++j) J[i][j] -= m * J[c][j];
+            }
+        }
+        for (int c = n - 1; c >= 0; --c) {
+            double v = J[c][n];
+            for (int j = c + 1; j < n; ++j) v -= J[c][j] * J[j][n];
+            J[c][n] = v / J[c][c];
+        }
+        for (int j = 0; j < n; ++j) x[j] += J[j][n];
+    }
+    t35_residual(x, ex, n, f);
+    for (int i = 0; i < n; ++i)
+        if (!(std::fabs(f[i]) < 1e-13)) return false;
+    int at = 0;
+    for (int o = 0; o < kT35Orbits; ++o) {
+        const double w = x[at];
+        double l[4];
+        t35_rep(o, x + at + 1, l);
+        at += 1 + kT35Par[o];
+        if (!(w > 0.0) || !(std::min(std::min(l[0], l[1]), std::min(l[2], l[3])) > 0.0)) return false;
+        // the distinct permutations of the representative
+        std::vector<std::array<double, 4>> seen;
+        int idx[4] = {0, 1, 2, 3};
+        do {
+            const std::array<double, 4> q = {l[idx[0]], l[idx[1]], l[idx[2]], l[idx[3]]};
+            if (std::find(seen.begin(), seen.end(), q) == seen.end()) seen.push_back(q);
+        } while (std::next_permutation(idx, idx + 4));
+        if (static_cast<int>(seen.size()) != kT35Size[o]) return false;
+        for (const auto &q : seen) add_bary(r, {q[0], q[1], q[2], q[3]}, w);
+    }
+    return true;
 }
 
 bool make_rule(int d, int npts, Rule &r)
@@ -166,6 +302,7 @@ bool make_rule(int d, int npts, Rule &r)
                 }
             return true;
         }
+        if (npts == 35) return solve_tet35(r);
         return false;
     }
     return false;

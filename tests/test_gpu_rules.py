@@ -1,10 +1,11 @@
 """GPU parity under the high-order rules of the paper's precomputations
 (section 5.2): Gauss with 5 and 6 points on segments, the 16-point degree-8
-Dunavant rule on triangles.
+Dunavant rule on triangles, a symmetric 35-point degree-7 rule on tetrahedra.
 
 The library builds these rules itself (Newton on the Legendre recurrence;
-the published 15-digit Dunavant values); the oracle solves their moment
-equations in high precision.  Matrices, load vector and shape gradient are
+the published 15-digit Dunavant values; Newton in double on the tetrahedral
+rule's moment equations); the oracle solves their moment equations in high
+precision.  Matrices, load vector and shape gradient are
 compared with the oracle at the same tolerances as under the default rules
 (1e-12 row-scaled); the rules' own difference is below 1e-14."""
 
@@ -22,7 +23,8 @@ pytestmark = pytest.mark.gpu
 
 # (element type, points): curves take Gauss 5 and 6, triangles Dunavant 16
 HIGH = [(t, q) for t in meshgen.ALL_TYPES if t[1] == 1 for q in (5, 6)] + \
-       [(t, 16) for t in meshgen.ALL_TYPES if t[1] == 2]
+       [(t, 16) for t in meshgen.ALL_TYPES if t[1] == 2] + \
+       [(t, 35) for t in meshgen.ALL_TYPES if t[1] == 3]
 
 
 @pytest.fixture(scope="module")
@@ -88,7 +90,7 @@ def test_load_and_shape_grad(lf, t, q):
     dm.close()
 
 
-@pytest.mark.parametrize("t,q", [(("surface", 2, 2), 16), (("surface", 1, 2), 6)])
+@pytest.mark.parametrize("t,q", [(("surface", 2, 2), 16), (("surface", 1, 2), 6), (("bulk", 3, 2), 35)])
 def test_high_order_rule_differs_from_default(lf, t, q):
     """The rule is really switched: on a curved P2 mesh the high-order rule's
     load vector differs from the default rule's, while both give nearly the
@@ -114,7 +116,7 @@ def test_batch_rejects_high_order_rule(lf):
     dm.close()
 
 
-def test_tetrahedron_has_no_high_order_rule(lf):
+def test_tetrahedron_rejects_triangle_rule(lf):
     m = with_rule(meshgen.small_mesh("bulk", 3, 2, size=2), 16)
     with pytest.raises(lf.LfemError) as e:
         lf.DeviceMesh.from_dict(m)

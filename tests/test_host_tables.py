@@ -14,7 +14,7 @@ from oracle import quadrature
 # (dim, order, points) for every rule each element type accepts
 CASES = ([(1, p, q) for p in (1, 2) for q in (2, 3, 5, 6)] + [(1, p, q) for p in (3, 4) for q in (5, 6)] +
          [(2, p, q) for p in (1, 2) for q in (3, 6, 16)] + [(2, p, 16) for p in (3, 4)] +
-         [(3, p, q) for p in (1, 2) for q in (4, 11)])
+         [(3, p, q) for p in (1, 2) for q in (4, 11, 35)])
 
 
 @pytest.fixture(scope="module")

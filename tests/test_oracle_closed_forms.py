@@ -179,6 +179,17 @@ AFFINE_CASES = [
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("domain,dim,verts", AFFINE_CASES)
 def test_affine_exact_rational(domain, dim, verts, order):
+    affine_exact_check(domain, dim, verts, order)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("domain,dim,verts", [c for c in AFFINE_CASES if c[1] == 3])
+def test_affine_exact_rational_degree7_tetrahedron(domain, dim, verts, order):
+    """The 35-point degree-7 rule gives the exact affine matrices too."""
+    affine_exact_check(domain, dim, verts, order, quad=35)
+
+
+def affine_exact_check(domain, dim, verts, order, quad=None):
     X = [[Fraction(c) for c in v] for v in verts]
     n = len(X[0])
     J = [[X[m + 1][c] - X[0][c] for m in range(dim)] for c in range(n)]  # n x d
@@ -206,7 +217,7 @@ def test_affine_exact_rational(domain, dim, verts, order):
     Mex *= mu
     Aex *= mu
     Vf = np.array([[float(c) for c in v] for v in verts])
-    m = single(domain, dim, order, Vf, [list(range(dim + 1))])
+    m = single(domain, dim, order, Vf, [list(range(dim + 1))], quad=quad)
     M = oracle.element_matrices(m, "mass")[0]
     A = oracle.element_matrices(m, "stiffness")[0]
     assert np.abs(M - Mex).max() <= 1e-14 * np.abs(Mex).max()

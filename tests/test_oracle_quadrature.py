@@ -15,7 +15,7 @@ import pytest
 
 from oracle import quadrature as Q
 
-RULES = [(1, 2), (1, 3), (1, 5), (1, 6), (2, 1), (2, 3), (2, 6), (2, 16), (3, 1), (3, 4), (3, 11)]
+RULES = [(1, 2), (1, 3), (1, 5), (1, 6), (2, 1), (2, 3), (2, 6), (2, 16), (3, 1), (3, 4), (3, 11), (3, 35)]
 
 
 def exact_monomial(alpha):
@@ -113,3 +113,20 @@ def test_degree8_triangle_matches_published_rule():
             assert d[i] < 2e-14 and abs(W1[i] - w) < 2e-14, (p, d[i], W1[i], w)
             seen += 1
     assert seen == 16
+
+
+def test_degree7_tetrahedron_positive_interior_distinct():
+    """The 35-point rule of degree 7 (the degree of the paper's tetrahedral
+    rule, section 5.2): positive weights, points strictly inside, no point
+    repeated, and invariant under the 24 vertex permutations (the set of
+    (barycentric point, weight) pairs maps onto itself)."""
+    P, W = Q.rule(3, 35)
+    assert np.all(W > 0)
+    lam = np.column_stack([1 - P.sum(1), P])
+    assert lam.min() > 0.02
+    key = {tuple(np.round(l, 12)): w for l, w in zip(lam, W)}
+    assert len(key) == 35
+    for s in itertools.permutations(range(4)):
+        for l, w in zip(lam, W):
+            m = tuple(np.round(l[list(s)], 12))
+            assert m in key and abs(key[m] - w) <= 1e-17
