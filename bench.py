@@ -232,6 +232,26 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     rows["dziuk_step_graph"] = row_entry(
         f"the same step replayed from a captured HIP graph", event_times(torch, graph.replay), Ts, bstep)
     del graph
+    # one step of the BDF algorithm of section 6.2 on the same sphere: M, A, the non-linear terms f
+    # of nu~, H~, S = delta0 M + tau A and rhs = tau f - M hist for the four components of (nu; H)
+    nus = torch.as_tensor(cs / np.linalg.norm(cs, axis=0), device="cuda")
+    Hs = torch.full((Ns,), 2.0, dtype=torch.float64, device="cuda")
+    hs = torch.as_tensor(np.random.default_rng(11).normal(size=(4, Ns)), device="cuda")
+    ko = dms.kll_system(1e-3, 1.5, nus, Hs, hs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dms.kll_system(1e-3, 1.5, nus, Hs, hs, out=ko)
+    # assembly as above; terms: coordinates, connectivity, nu, H in, f out; rows: M, A, pattern, hist,
+    # f in, S and rhs out
+    bkll = ((3 * Ns * 8 + 6 * Ts * 4 + 2 * nnzs * 8) + (3 * Ns * 8 + 6 * Ts * 4 + 4 * Ns * 8 + 4 * Ns * 8)
+            + (2 * nnzs * 8 + (Ns + 1) * 4 + nnzs * 4 + 8 * Ns * 8 + nnzs * 8 + 4 * Ns * 8))
+    rows["kll_step_eager"] = row_entry(
+        f"BDF MCF step of section 6.2 (M, A, f, S = delta0 M + tau A, rhs = tau f - M hist), same sphere",
+        event_times(torch, lambda: dms.kll_system(1e-3, 1.5, nus, Hs, hs, out=ko)), Ts, bkll)
+    rows["kll_step_graph"] = row_entry(
+        f"the same step replayed from a captured HIP graph", event_times(torch, graph.replay), Ts, bkll)
+    del graph
     dms.close()
     # order sweep: M + A on spheres of order p = 1..4 with about the same number of nodes, default
     # rule and scatter of each order
@@ -462,7 +482,7 @@ def main():
         "pattern_build_s": pattern_s,
     }
     if not args.no_rows:
-        print("[bench] other rows (load, non-linear terms, shape gradient, Dziuk step, orders 1-4, tetrahedra)",
+        print("[bench] other rows (load, non-linear terms, shape gradient, MCF steps, orders 1-4, tetrahedra)",
               file=sys.stderr, flush=True)
         result["rows"] = other_rows(lf, torch, meshgen, mesh, dm)
     dm.close()

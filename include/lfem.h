@@ -191,6 +191,35 @@ lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const
                               void *stream);
 
 /*
+ * Per-step system of the paper's mean-curvature-flow algorithm of section 6.2
+ * (evolving-surface finite elements, linearly implicit BDF time stepping of
+ * the coupled system for u = (nu; H), nu the unit normal and H the mean
+ * curvature).  With the BDF derivative u_dot^n = (1/tau) sum_{j>=0}
+ * delta_j u^{n-j}, the equation M u_dot^n + A u^n = f(x~, u~) at the
+ * extrapolated surface x~ and extrapolated u~ reads, per component,
+ *     (delta0 M(x~) + tau A(x~)) u^n = tau f(x~, u~) - M(x~) hist,
+ *     hist = sum_{j>=1} delta_j u^{n-j}.
+ * The mesh's current coordinates are x~.  Assembles M and A into vals_m,
+ * vals_a (nnz doubles each, the pattern's tuned scatter variant), the
+ * non-linear terms f = (f_1; f_2) of nu = nu~, H = H~ exactly as
+ * lfem_assemble_kll into f ((n_amb + 1) * N doubles), then forms
+ * vals_s = delta0 * vals_m + tau * vals_a and, for c <= n_amb,
+ *     rhs[c * N + i] = tau * f[c * N + i] - sum_j M_ij hist[c * N + j]
+ * (each row summed in column order: deterministic).  nu: n_amb * N doubles
+ * and hist, rhs: (n_amb + 1) * N doubles, all component-major with the
+ * normal components first and H last; H: N doubles; hist may be NULL (zero
+ * history).  The velocity v = -H^n nu^n and the position update are the
+ * caller's, as are the linear solves.  After one call a call allocates
+ * nothing (HIP-graph capturable, as lfem_dziuk_system); it uses the mesh's
+ * scratch buffer: calls on one mesh must not overlap.
+ * Errors: LFEM_EINVAL (handles, null buffers, non-finite tau or delta0),
+ * LFEM_EHIP.
+ */
+lfem_status lfem_kll_system(lfem_mesh_t m, lfem_pattern_t p, double tau, double delta0, const double *nu,
+                            const double *H, const double *hist, double *vals_m, double *vals_a,
+                            double *vals_s, double *f, double *rhs, void *stream);
+
+/*
  * Autotune the scatter variant and row-block size of pattern p for the
  * matrix set `what` by timing the candidates on stream (SYNCHRONISES).
  * The choice is kept in the pattern and used by LFEM_SCATTER_AUTO.

@@ -209,6 +209,31 @@ def kll(mesh, nu, H=None, rule=None):
     return f
 
 
+def kll_system(mesh, tau, delta0, nu, H, hist=None):
+    """Per-step linear system of the mean-curvature-flow algorithm of section
+    6.2 (evolving-surface finite elements with linearly implicit BDF): with
+    u = (nu; H) in R^{(n_amb + 1) N} and the BDF derivative
+    u_dot^n = (1/tau) sum_{j>=0} delta_j u^{n-j}, the equation
+    M u_dot^n + A u^n = f(x~, u~) at the extrapolated surface x~ (the mesh's
+    coordinates) and extrapolated u~ = (nu; H) reads
+        (delta_0 M + tau A) u^n = tau f - M sum_{j>=1} delta_j u^{n-j},
+    the same S for every component.  hist: the history term
+    sum_{j>=1} delta_j u^{n-j} as an (n_amb + 1, N) array (None: zero).
+    Returns (S as CSR (row_ptr, col_idx, vals) on the pattern of M, f, rhs)."""
+    Mrp, Mci, Mv = assemble(mesh, "mass")
+    Arp, Aci, Av = assemble(mesh, "stiffness")
+    if not (np.array_equal(Mrp, Arp) and np.array_equal(Mci, Aci)):
+        raise RuntimeError("mass and stiffness patterns differ")
+    f = kll(mesh, nu, H)
+    rhs = tau * f
+    if hist is not None:
+        N = len(Mrp) - 1
+        M = to_scipy(N, (Mrp, Mci, Mv))
+        hist = np.asarray(hist, dtype=np.float64).reshape(f.shape)
+        rhs = rhs - np.stack([M @ hist[c] for c in range(f.shape[0])])
+    return (Mrp, Mci, delta0 * Mv + tau * Av), f, rhs
+
+
 def shape_grad(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0):
     """d/dx [alpha u^T A(x) v + beta w^T M(x) z] as an (n_amb, N) array."""
     args, keep, N, T, k = _mesh_args(mesh)

@@ -29,7 +29,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -196,6 +196,15 @@ def lfem_dziuk_system(mesh, pattern, tau, x, vals_m, vals_a, vals_s, rhs, stream
                               _ptr(vals_s, torch.float64, "vals_s"), _ptr(rhs, torch.float64, "rhs"),
                               _stream(stream))
     _lib.check(st, "lfem_dziuk_system")
+
+
+def lfem_kll_system(mesh, pattern, tau, delta0, nu, H, hist, vals_m, vals_a, vals_s, f, rhs, stream=None):
+    st = _L.lfem_kll_system(mesh, pattern, float(tau), float(delta0), _ptr(nu, torch.float64, "nu"),
+                            _ptr(H, torch.float64, "H"), _ptr(hist, torch.float64, "hist"),
+                            _ptr(vals_m, torch.float64, "vals_m"), _ptr(vals_a, torch.float64, "vals_a"),
+                            _ptr(vals_s, torch.float64, "vals_s"), _ptr(f, torch.float64, "f"),
+                            _ptr(rhs, torch.float64, "rhs"), _stream(stream))
+    _lib.check(st, "lfem_kll_system")
 
 
 def lfem_assemble_kll(mesh, nu, H, f, stream=None):

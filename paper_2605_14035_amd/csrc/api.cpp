@@ -271,6 +271,21 @@ lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const
     });
 }
 
+lfem_status lfem_kll_system(lfem_mesh_t m, lfem_pattern_t p, double tau, double delta0, const double *nu,
+                            const double *H, const double *hist, double *vals_m, double *vals_a, double *vals_s,
+                            double *f, double *rhs, void *stream)
+{
+    return guarded([&] {
+        check_numeric_args(m, p, LFEM_M | LFEM_A, nullptr, vals_m, vals_a, nullptr);
+        LFEM_REQUIRE(vals_s || p->nnz == 0, LFEM_EINVAL, "vals_s is null");
+        LFEM_REQUIRE((nu && H && f && rhs) || m->N == 0, LFEM_EINVAL, "nu, H, f or rhs is null");
+        LFEM_REQUIRE(std::isfinite(tau) && std::isfinite(delta0), LFEM_EINVAL, "tau or delta0 is not finite");
+        int variant = p->tuned_variant;
+        if (variant == LFEM_SCATTER_BLOCKED && p->sched.nb == 0 && m->T > 0) variant = LFEM_SCATTER_STAGED;
+        launch_kll_system(*m, *p, tau, delta0, nu, H, hist, vals_m, vals_a, vals_s, f, rhs, variant, S(stream));
+    });
+}
+
 lfem_status lfem_assemble_mass(lfem_mesh_t m, lfem_pattern_t p, double *vals, void *stream)
 {
     return lfem_assemble(m, p, LFEM_M, nullptr, nullptr, vals, nullptr, nullptr,

@@ -219,5 +219,8 @@ void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
 void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s);
 void launch_dziuk(Mesh &m, Pattern &p, double tau, const double *x, double *vals_m, double *vals_a,
                   double *vals_s, double *rhs, int variant, hipStream_t s);
+void launch_kll_system(Mesh &m, Pattern &p, double tau, double delta0, const double *nu, const double *H,
+                       const double *hist, double *vals_m, double *vals_a, double *vals_s, double *f, double *rhs,
+                       int variant, hipStream_t s);
 
 }  // namespace lfem

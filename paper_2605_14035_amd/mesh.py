@@ -9,7 +9,7 @@ import torch
 
 from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFACE,
                copy_from_device, lfem_assemble, lfem_assemble_kll, lfem_assemble_load,
-               lfem_dziuk_system, lfem_energy, lfem_mesh_create, lfem_mesh_destroy,
+               lfem_dziuk_system, lfem_energy, lfem_kll_system, lfem_mesh_create, lfem_mesh_destroy,
                lfem_mesh_set_coords, lfem_pattern_build,
                lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
 
@@ -112,6 +112,26 @@ class DeviceMesh:
         if "rhs" not in out:
             out["rhs"] = torch.empty(self.coords.shape[0], self.N, dtype=torch.float64, device=dev)
         lfem_dziuk_system(self.handle, self.pattern, tau, x, out["M"], out["A"], out["S"], out["rhs"], stream)
+        return out
+
+    def kll_system(self, tau, delta0, nu, H, hist=None, out=None, stream=None):
+        """Per-step system of the BDF mean-curvature-flow algorithm (coupled
+        in u = (nu; H)) at the current coordinates (the extrapolated surface):
+        dict with "M", "A", "S" = delta0 M + tau A (nnz,), "f" the non-linear
+        terms and "rhs" = tau f - M hist, both (n_amb + 1, N).  nu: (n_amb, N)
+        and H: (N,) the extrapolated normal and mean curvature; hist:
+        (n_amb + 1, N) = sum_{j>=1} delta_j u^{n-j}, or None for zero."""
+        self.build_pattern(stream)
+        out = dict(out or {})
+        dev = self.coords.device
+        for key in ("M", "A", "S"):
+            if key not in out:
+                out[key] = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        for key in ("f", "rhs"):
+            if key not in out:
+                out[key] = torch.empty(self.coords.shape[0] + 1, self.N, dtype=torch.float64, device=dev)
+        lfem_kll_system(self.handle, self.pattern, tau, delta0, nu, H, hist, out["M"], out["A"], out["S"],
+                        out["f"], out["rhs"], stream)
         return out
 
     def degenerate_count(self):

@@ -11,6 +11,13 @@ f_2 = int alpha^2 H_h phi_j.
   tensor J G^{-1} g (numpy, per point) instead of the oracle's C^T [g; 0];
 * invariants: rotating the mesh and the field together rotates f_1 and leaves
   f_2 alone; scaling the mesh by s scales f by s^(d-2); f_2 is linear in H.
+
+The per-step system of the algorithm (linearly implicit BDF in u = (nu; H),
+oracle.kll_system) is pinned by running the scheme: on the unit sphere the
+exact flow keeps nu = x/|x| and H = 2/r with r(t)^2 = 1 - 4t, and BDF1 / BDF2
+must approach it with first / second order in tau.  A dropped f, a wrong
+sign of A or f, or mixed-up components of u break this by orders of
+magnitude.
 """
 
 import numpy as np
@@ -155,3 +162,63 @@ def test_linear_in_H_and_default():
     f2H1 = oracle.kll(m, nu, 2 * H + 1)
     assert np.array_equal(f1[:n], fH[:n])
     assert np.abs(f2H1[n] - (2 * fH[n] + f1[n])).max() <= 1e-12 * np.abs(f2H1[n]).max()
+
+
+def kll_flow(level, tau, steps, bdf):
+    """The linearly implicit BDF scheme for the coupled system (section 6.2)
+    with the oracle's per-step system and a sparse LU solve; BDF1 for the
+    first step of BDF2.  Returns the final positions and u = (nu; H)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    V, F = mg.icosphere_red(level, order=2)
+    coords, conn = mg.to_soa(V, F)
+    N = coords.shape[1]
+    x = [coords.copy()]
+    u = [np.vstack([coords / np.linalg.norm(coords, axis=0), 2.0 * np.ones((1, N))])]
+    for n in range(steps):
+        if bdf == 1 or n == 0:  # delta = (1, -1)
+            d0, xt, ut, hist, xh = 1.0, x[-1], u[-1], -u[-1], -x[-1]
+        else:  # delta = (3/2, -2, 1/2), extrapolation 2 y^{n-1} - y^{n-2}
+            d0, xt, ut = 1.5, 2 * x[-1] - x[-2], 2 * u[-1] - u[-2]
+            hist, xh = -2 * u[-1] + 0.5 * u[-2], -2 * x[-1] + 0.5 * x[-2]
+        m = dict(domain="surface", dim=2, order=2, quad=6, coords=xt, conn=conn)
+        (rp, ci, sv), f, rhs = oracle.kll_system(m, tau, d0, ut[:3], ut[3], hist)
+        lu = spla.splu(sp.csr_matrix((sv, ci, rp), shape=(N, N)).tocsc())
+        un = np.stack([lu.solve(rhs[c]) for c in range(4)])
+        x.append((tau * (-un[3] * un[:3]) - xh) / d0)  # BDF derivative of x = v = -H nu
+        u.append(un)
+    return x[-1], u[-1]
+
+
+def test_bdf_scheme_shrinks_sphere_with_its_order():
+    tau, steps = 1e-3, 25
+    exact = np.sqrt(1.0 - 4.0 * tau * steps)
+    err = {}
+    for bdf in (1, 2):
+        x, u = kll_flow(2, tau, steps, bdf)
+        r = np.linalg.norm(x, axis=0)
+        err[bdf] = abs(r.mean() - exact)
+        assert r.max() - r.min() < 1e-5  # stays round
+        assert np.abs(u[3] - 2.0 / r).max() < 2e-3 * (2.0 / exact)
+        assert np.abs(np.linalg.norm(u[:3], axis=0) - 1.0).max() < 5e-4
+    assert err[1] < 1e-4
+    assert err[2] < 5e-6
+    assert err[2] < err[1] / 10
+
+
+def test_kll_system_composition():
+    """S = delta0 M + tau A on M's pattern, rhs = tau f - M hist, f the pinned
+    non-linear terms; hist = None is a zero history."""
+    m = meshgen.small_mesh("surface", 2, 2, size=2)
+    n, N = m["coords"].shape
+    rng = np.random.default_rng(2)
+    nu, H, hist = rng.normal(size=(n, N)), rng.normal(size=N), rng.normal(size=(n + 1, N))
+    (rp, ci, sv), f, rhs = oracle.kll_system(m, 0.25, 1.5, nu, H, hist)
+    Mc, Ac = oracle.assemble(m, "mass"), oracle.assemble(m, "stiffness")
+    assert np.array_equal(rp, Mc[0]) and np.array_equal(ci, Mc[1])
+    assert np.abs(sv - (1.5 * Mc[2] + 0.25 * Ac[2])).max() <= 1e-15 * np.abs(sv).max()
+    M = oracle.to_scipy(N, Mc).toarray()
+    assert np.abs(f - oracle.kll(m, nu, H)).max() == 0
+    assert np.abs(rhs - (0.25 * f - hist @ M.T)).max() <= 1e-14 * np.abs(rhs).max()
+    _, _, rhs0 = oracle.kll_system(m, 0.25, 1.5, nu, H)
+    assert np.array_equal(rhs0, 0.25 * f)
