@@ -157,7 +157,10 @@ lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
  * weighted mass (required with LFEM_MC).  vals_m / vals_a / vals_mc: outputs
  * of nnz doubles each, overwritten (required for the selected matrices).
  * scatter: LFEM_SCATTER_*.  The blocked and staged scatters are bitwise
- * reproducible run to run; the atomic one is not.
+ * reproducible run to run; the atomic one is not.  The first staged call on
+ * a pattern builds its contribution lists and SYNCHRONISES stream once;
+ * later calls are asynchronous and allocate nothing while the staging
+ * buffer suffices.
  * Degenerate elements (measure not positive and finite) still produce values
  * and increment the mesh's counter (lfem_status_get).
  */

@@ -84,6 +84,7 @@ void release_pattern(Pattern &p)
     dev_free(p.off8);
     dev_free(p.cptr);
     dev_free(p.clist);
+    dev_free(p.long_slots);
     dev_free(p.stage);
     free_schedule(p.sched);
 }

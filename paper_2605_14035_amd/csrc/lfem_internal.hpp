@@ -68,6 +68,10 @@ inline int etype_of(int domain, int d, int p)
 // largest element (quartic triangle) and the 32-bit words of its k x k
 // byte slot map
 constexpr int kMaxNodes = 15;
+// contributions of one CSR value loaded at once by the staged reduction; the
+// values with longer lists (diagonals of well-connected nodes) are summed by
+// a second, small launch so that the main one needs a single round of loads
+constexpr int kReduceBatch = 8;
 constexpr int kMaxSlotWords = (kMaxNodes * kMaxNodes + 3) / 4;
 
 // nodes of the order-p Lagrange element: (p + d choose d)
@@ -165,6 +169,8 @@ struct Pattern {
     // staged scatter (built on first use)
     int32_t *cptr = nullptr;   // [nnz+1]
     int32_t *clist = nullptr;  // [k*k*T] contributions e*256 + a*k + b, ascending per slot
+    int32_t *long_slots = nullptr;  // [nlong] slots with more than kReduceBatch contributions, ascending
+    int64_t nlong = 0;
     double *stage = nullptr;
     size_t stage_bytes = 0;
     // blocked scatter

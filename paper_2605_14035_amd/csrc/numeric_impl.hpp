@@ -158,25 +158,20 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
     }
 }
 
+// sum of the contributions of CSR value s, in ascending element order, up to
+// kReduceBatch loads in flight
 template <int K, int NMAT>
-__global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
-                                                const int32_t *__restrict__ cptr,
-                                                const int32_t *__restrict__ clist,
-                                                const double *__restrict__ stage,
-                                                double *__restrict__ v0, double *__restrict__ v1,
-                                                double *__restrict__ v2)
+__device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t c_end,
+                                            const int32_t *__restrict__ clist,
+                                            const double *__restrict__ stage, double *const (&outs)[3])
 {
     constexpr int NP = K * (K + 1) / 2;
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= nnz) return;
+    constexpr int U = kReduceBatch;
     double acc[NMAT];
 #pragma unroll
     for (int mat = 0; mat < NMAT; ++mat) acc[mat] = 0.0;
-    // up to U contributions in flight, added in ascending element order
-    constexpr int U = 8;
-    const int32_t end = cptr[s + 1];
-    for (int32_t c0 = cptr[s]; c0 < end; c0 += U) {
-        const int cnt = min(U, end - c0);
+    for (int32_t c0 = c_begin; c0 < c_end; c0 += U) {
+        const int cnt = min(U, c_end - c0);
         int32_t code[U];
         double v[U][NMAT];
 #pragma unroll
@@ -198,9 +193,41 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, int64_t T,
                 for (int mat = 0; mat < NMAT; ++mat) acc[mat] += v[i][mat];
             }
     }
-    double *outs[3] = {v0, v1, v2};
 #pragma unroll
     for (int mat = 0; mat < NMAT; ++mat) outs[mat][s] = acc[mat];
+}
+
+// one thread per CSR value with at most kReduceBatch contributions (a single
+// round of loads); the longer lists are left to k_reduce_long
+template <int K, int NMAT>
+__global__ __launch_bounds__(256) void k_reduce(int64_t nnz, const int32_t *__restrict__ cptr,
+                                                const int32_t *__restrict__ clist,
+                                                const double *__restrict__ stage,
+                                                double *__restrict__ v0, double *__restrict__ v1,
+                                                double *__restrict__ v2)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= nnz) return;
+    const int32_t c0 = cptr[s], c1 = cptr[s + 1];
+    if (c1 - c0 > kReduceBatch) return;
+    double *const outs[3] = {v0, v1, v2};
+    reduce_slot<K, NMAT>(s, c0, c1, clist, stage, outs);
+}
+
+// one thread per listed CSR value with a long list (same order of summation)
+template <int K, int NMAT>
+__global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_t *__restrict__ slots,
+                                                     const int32_t *__restrict__ cptr,
+                                                     const int32_t *__restrict__ clist,
+                                                     const double *__restrict__ stage,
+                                                     double *__restrict__ v0, double *__restrict__ v1,
+                                                     double *__restrict__ v2)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nlong) return;
+    const int64_t s = slots[i];
+    double *const outs[3] = {v0, v1, v2};
+    reduce_slot<K, NMAT>(s, cptr[s], cptr[s + 1], clist, stage, outs);
 }
 
 template <class E, int NM, bool HA, int NT>
@@ -381,9 +408,15 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             k_stage<E, Q, NM, HA><<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q>(), s>>>(g, m.T, m.conn, p.stage);
         });
         LFEM_HIP(hipGetLastError());
-        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, m.T, p.cptr, p.clist,
-                                                                   p.stage, o.v[0], o.v[1], o.v[2]);
+        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
+                                                                   o.v[1], o.v[2]);
         LFEM_HIP(hipGetLastError());
+        if (p.nlong > 0) {
+            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
+                                                                             p.clist, p.stage, o.v[0], o.v[1],
+                                                                             o.v[2]);
+            LFEM_HIP(hipGetLastError());
+        }
         return;
     }
     // blocked (block schedules exist for orders 1 and 2 only)

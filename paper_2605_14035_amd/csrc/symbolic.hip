@@ -343,6 +343,23 @@ X *dev_alloc(size_t count)
     return p;
 }
 
+// flag[s] = 1 if slot s has more than kReduceBatch contributions
+__global__ __launch_bounds__(256) void k_long_flag(int64_t nnz, const int32_t *__restrict__ cptr,
+                                                   int32_t *__restrict__ flag)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= nnz) return;
+    flag[s] = cptr[s + 1] - cptr[s] > kReduceBatch ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_long_fill(int64_t nnz, const int32_t *__restrict__ flag,
+                                                   const int32_t *__restrict__ pos, int32_t *__restrict__ out)
+{
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= nnz) return;
+    if (flag[s]) out[pos[s]] = static_cast<int32_t>(s);
+}
+
 }  // namespace
 
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *d_total,
@@ -480,6 +497,26 @@ void build_staged(Mesh &m, Pattern &p, hipStream_t s)
     if (p.nnz > 0) {
         k_sort_lists<<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist);
         LFEM_HIP(hipGetLastError());
+    }
+    // the slots with long lists, in ascending order: flag, scan, fill
+    p.nlong = 0;
+    if (p.nnz > 0) {
+        int32_t *pos = nullptr;
+        LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&pos), (p.nnz + 1) * sizeof(int32_t), s));
+        k_long_flag<<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, cnt);
+        LFEM_HIP(hipGetLastError());
+        exclusive_scan_i32(cnt, pos, p.nnz, tot, s);
+        int64_t nlong = 0;
+        LFEM_HIP(hipMemcpyAsync(&nlong, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LFEM_HIP(hipStreamSynchronize(s));
+        LFEM_REQUIRE(nlong >= 0 && nlong <= p.nnz, LFEM_EHIP, "long-list count out of range");
+        p.nlong = nlong;
+        p.long_slots = dev_alloc<int32_t>(nlong);
+        if (nlong > 0) {
+            k_long_fill<<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, cnt, pos, p.long_slots);
+            LFEM_HIP(hipGetLastError());
+        }
+        LFEM_HIP(hipFreeAsync(pos, s));
     }
     LFEM_HIP(hipFreeAsync(cnt, s));
     LFEM_HIP(hipFreeAsync(tot, s));
