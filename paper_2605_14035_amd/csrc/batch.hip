@@ -51,14 +51,18 @@ namespace {
 
 constexpr int BATCH_NT = kSideThreads;
 
+// one work item; thread 0 claims the workgroup's next item once this item's
+// loads are issued, so the claim's round trip overlaps the item's compute
 template <class E, int NM, bool HA>
-__device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *lds, int dump, int rs)
+__device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *lds, int dump, int rs,
+                                           int *__restrict__ counter, int &next)
 {
     constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
     SideBlock<E> s;
     side_load_rec<E>(g, blk, s);
     side_load_first<E>(g, s);
     side_load_coords<E>(g, s);
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     if (g.Q == QA) side_block<E, QA, NM, HA, 0, BATCH_NT>(g, s, lds, dump, rs);
     else side_block<E, QB, NM, HA, 0, BATCH_NT>(g, s, lds, dump, rs);
 }
@@ -74,22 +78,28 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch(const BlockArgs *__restrict_
     extern __shared__ double lds[];
     __shared__ int cur;
     for (int i = threadIdx.x; i < NMAT * rs; i += BATCH_NT) lds[i] = 0.0;
+    int next = 0;  // thread 0: the claimed next item
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     for (;;) {
-        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) cur = next;
         __syncthreads();
         const int it = cur;
         __syncthreads();
-        if (it >= n_items) break;  // uniform: every workgroup leaves once the list is drained
+        // uniform: every workgroup leaves once its claim is past the list (each
+        // item below n_items is claimed once and processed by its claimer)
+        if (it >= n_items) break;
         const int2 w = items[it];
         const BlockArgs g = desc[w.x];
         switch (g.etype) {
-        case S1P1: batch_item<ET<1, 1, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
-        case S1P2: batch_item<ET<1, 1, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
-        case S2P1: batch_item<ET<1, 2, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
-        case S2P2: batch_item<ET<1, 2, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
-        case B2P1: batch_item<ET<0, 2, 1>, NM, HA>(g, w.y, lds, dump, rs); break;
-        case B2P2: batch_item<ET<0, 2, 2>, NM, HA>(g, w.y, lds, dump, rs); break;
-        default: break;
+        case S1P1: batch_item<ET<1, 1, 1>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        case S1P2: batch_item<ET<1, 1, 2>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        case S2P1: batch_item<ET<1, 2, 1>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        case S2P2: batch_item<ET<1, 2, 2>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        case B2P1: batch_item<ET<0, 2, 1>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        case B2P2: batch_item<ET<0, 2, 2>, NM, HA>(g, w.y, lds, dump, rs, counter, next); break;
+        default:
+            if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+            break;
         }
     }
 }

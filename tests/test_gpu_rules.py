@@ -17,7 +17,7 @@ import torch
 
 import meshgen
 import oracle
-from gpu_util import assert_csr_close
+from gpu_util import assert_csr_close, assert_rows_close
 
 pytestmark = pytest.mark.gpu
 
@@ -121,3 +121,29 @@ def test_tetrahedron_rejects_triangle_rule(lf):
     with pytest.raises(lf.LfemError) as e:
         lf.DeviceMesh.from_dict(m)
     assert e.value.status == lf.LFEM_EUNSUPPORTED
+
+
+def test_config3_degree7_full_size_sampled(lf):
+    """The 1,572,864-tetrahedron workload under the 35-point degree-7 rule, in
+    the launch the benchmark row times (scatter chosen by the autotuner, M and
+    A_a in one call): sampled rows against the oracle under the same rule,
+    1^T M 1 = 1 and A_a 1 = 0."""
+    m = dict(meshgen.config3(), quad=35)
+    say("config3 full size, 35-point rule")
+    dm = lf.DeviceMesh.from_dict(m)
+    dm.build_pattern()
+    lf.lfem_pattern_autotune(dm.handle, dm.pattern, lf.LFEM_M | lf.LFEM_A)
+    ca = torch.as_tensor(m["coef_a"], device="cuda")
+    out = dm.assemble(lf.LFEM_M | lf.LFEM_A, coef_a=ca)
+    assert abs(float(out["M"].sum().item()) - 1.0) < 1e-12
+    rp_t, ci_t = dm.pattern_tensors()
+    rows_t = torch.repeat_interleave(torch.arange(dm.N, device="cuda"), (rp_t[1:] - rp_t[:-1]).long())
+    a1 = torch.zeros(dm.N, dtype=torch.float64, device="cuda").index_add_(0, rows_t, out["A"])
+    amax = torch.zeros(dm.N, dtype=torch.float64, device="cuda").index_reduce_(0, rows_t, out["A"].abs(), "amax")
+    assert float((a1.abs() / amax).max().item()) < 1e-12
+    rp, ci = rp_t.cpu().numpy(), ci_t.cpu().numpy()
+    rows = np.unique(np.random.default_rng(13).integers(0, dm.N, 200))
+    for key, kind, c in (("M", "mass", None), ("A", "stiffness", m["coef_a"])):
+        ref = oracle.assemble(m, kind, coef=c, rows=rows)
+        assert_rows_close(rp, ci, out[key].cpu().numpy(), ref, rows, what=f"c3 Q=35 {key}")
+    dm.close()

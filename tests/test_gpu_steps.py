@@ -28,7 +28,7 @@ import torch
 
 import meshgen
 import oracle
-from gpu_util import assert_csr_close
+from gpu_util import assert_csr_close, assert_rows_close
 from meshgen import meshes as mg
 
 pytestmark = pytest.mark.gpu
@@ -252,4 +252,40 @@ def test_kll_system_bad_arguments(lf):
     with pytest.raises(lf.LfemError) as e:
         dm.kll_system(1e-3, 1.0, nu, None)
     assert e.value.status == lf.LFEM_EINVAL
+    dm.close()
+
+
+def test_kll_system_config2_sampled(lf):
+    """The BDF step on the 655,360-element P2 ellipsoid with its normals as nu,
+    a nodal H and a random history: f over every node, S and rhs on sampled
+    rows, against the oracle."""
+    m = meshgen.config2()
+    say("config2 kll system")
+    dm = lf.DeviceMesh.from_dict(m)
+    X = m["coords"]
+    n, N = X.shape
+    g = X / np.array([1.0, 0.64, 0.36])[:, None]
+    nu = g / np.linalg.norm(g, axis=0)
+    H = m["coef_c"]
+    hist = np.random.default_rng(12).normal(size=(n + 1, N))
+    tau, d0 = 2e-3, 1.5
+    out = dm.kll_system(tau, d0, *(torch.as_tensor(np.ascontiguousarray(v), device="cuda") for v in (nu, H, hist)))
+    fo = oracle.kll(m, nu, H)
+    f = out["f"].cpu().numpy()
+    for c in range(n + 1):
+        assert np.abs(f[c] - fo[c]).max() <= 1e-12 * np.abs(fo[c]).max(), c
+    rp, ci = (v.cpu().numpy() for v in dm.pattern_tensors())
+    rows = np.unique(np.random.default_rng(14).integers(0, N, 300))
+    Mr = oracle.assemble(m, "mass", rows=rows)
+    Ar = oracle.assemble(m, "stiffness", rows=rows)
+    Sr = (Mr[0], Mr[1], d0 * Mr[2] + tau * Ar[2])
+    assert_rows_close(rp, ci, out["S"].cpu().numpy(), Sr, rows, what="c2 S")
+    rhs = out["rhs"].cpu().numpy()
+    for i in rows:
+        a, b = Mr[0][i], Mr[0][i + 1]
+        cols, mv = Mr[1][a:b], Mr[2][a:b]
+        for c in range(n + 1):
+            ref = tau * fo[c, i] - mv @ hist[c, cols]
+            scale = tau * abs(fo[c, i]) + np.abs(mv) @ np.abs(hist[c, cols])
+            assert abs(rhs[c, i] - ref) <= 1e-12 * scale, (i, c)
     dm.close()
