@@ -17,10 +17,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 const char *last_error() { return g_last_error.c_str(); }
 
-// defaults of the blocked scatter's schedule: values per block and matrix
-// (with two matrices, M + A, two workgroups still fit in one CU's 160 KB of
-// LDS) and rows per block
-constexpr int kDefaultCap = 4864;
+// rows per block of the blocked scatter's default schedule
 constexpr int kMaxRows = kBlockMaxRows;
 
 }  // namespace lfem
@@ -192,7 +189,7 @@ lfem_status lfem_pattern_build(lfem_mesh_t m, void *stream, lfem_pattern_t *out)
             build_pattern(*m, *p, S(stream));
             if (m->N > 0 && m->T > 0) {
                 try {
-                    build_schedule(*m, *p, std::max(kDefaultCap, p->max_row), kMaxRows, S(stream));
+                    build_schedule(*m, *p, default_block_cap(p->max_row), kMaxRows, S(stream));
                 } catch (const Error &e) {
                     if (e.code != LFEM_EUNSUPPORTED) throw;
                     p->tuned_variant = LFEM_SCATTER_STAGED;  // no block schedule possible

@@ -183,6 +183,15 @@ struct Pattern {
 // most rows of one block (row offsets are staged in LDS; the side-slot kernels
 // hold (kBlockMaxRows + 1) / nthreads of them per thread)
 constexpr int kBlockMaxRows = 1024;
+// default values per block and matrix of the blocked scatter: the largest
+// capacity up to kBlockCapDefault at which two M + A workgroups of the
+// side-slot kernel (2 x (cap + dump entries) doubles each) fit in one CU's
+// 160 KB of LDS.  On the 655,360-element P2 ellipsoid 4992 leaves fewer
+// blocks than seven rounds of 512 workgroups take (3550), where 4864 left
+// 13 blocks for an eighth round (about 2 % slower).
+constexpr int kBlockCapDefault = 4992;
+constexpr int kTwoGroupLdsDoubles = 160 * 1024 / 2 / 2 / 8;  // per matrix
+int default_block_cap(int max_row);
 
 // ---------------------------------------------------------------------------
 // symbolic phase (symbolic.hip)

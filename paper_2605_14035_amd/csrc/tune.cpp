@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "lfem_internal.hpp"
+#include "side.hpp"
 
 namespace lfem {
 
@@ -53,6 +54,11 @@ float time_variant(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStr
 
 }  // namespace
 
+int default_block_cap(int max_row)
+{
+    return std::max(max_row, std::min(kBlockCapDefault, kTwoGroupLdsDoubles - side_dump_entries(max_row)));
+}
+
 int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
 {
     if (m.T == 0 || p.nnz == 0) return p.tuned_variant;
@@ -70,7 +76,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s)
     const char *env = std::getenv("LFEM_TUNE_VERBOSE");
     const bool verbose = env && env[0] == '1';
     try {
-        const int caps[] = {2048, 3072, 4096, 4864, 6144, 8192};
+        const int caps[] = {2048, 3072, 4096, 4864, 4992, 6144, 8192};
         for (int cap : caps) {
             if (cap < p.max_row) continue;
             if (static_cast<size_t>(nmat) * cap * 8 + 4 * 1025 > 160 * 1024) continue;
