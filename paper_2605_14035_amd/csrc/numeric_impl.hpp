@@ -193,8 +193,10 @@ __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t 
                 for (int mat = 0; mat < NMAT; ++mat) acc[mat] += v[i][mat];
             }
     }
+    // written once, not read again here: non-temporal (the staged values that
+    // neighbouring rows still gather stay in the caches)
 #pragma unroll
-    for (int mat = 0; mat < NMAT; ++mat) outs[mat][s] = acc[mat];
+    for (int mat = 0; mat < NMAT; ++mat) __builtin_nontemporal_store(acc[mat], &outs[mat][s]);
 }
 
 // one thread per CSR value with at most kReduceBatch contributions (a single
