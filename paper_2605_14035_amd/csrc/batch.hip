@@ -60,7 +60,7 @@ __device__ __forceinline__ void batch_item(const BlockArgs &g, int blk, double *
     constexpr int QA = E::d == 1 ? 2 : 3, QB = E::d == 1 ? 3 : 6;
     SideBlock<E> s;
     side_load_rec<E>(g, blk, s);
-    side_load_first<E>(g, s);
+    side_load_first<E, true>(g, s);
     side_load_coords<E>(g, s);
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     if (g.Q == QA) side_block<E, QA, NM, HA, 0, BATCH_NT>(g, s, lds, dump, rs);

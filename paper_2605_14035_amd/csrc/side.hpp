@@ -80,32 +80,42 @@ __device__ __forceinline__ void side_load_rec(const BlockArgs &g, int blk, SideB
     s.o1 = r[7];
 }
 
-template <class E>
+// schedule words are read once per block; STREAM loads them non-temporally
+// (the batched kernel, whose many meshes stream through the caches: about
+// 5 % faster there, while the single-mesh kernel is faster without)
+template <bool STREAM, class T>
+__device__ __forceinline__ T sched_load(const T *p)
+{
+    if constexpr (STREAM) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <class E, bool STREAM = false>
 __device__ __forceinline__ void side_load_elem(const BlockArgs &g, int32_t idx, int32_t (&nid)[E::k],
                                                uint32_t (&ow)[SideLayout<E>::KW], uint32_t (&nw)[E::k])
 {
     using L = SideLayout<E>;
 #pragma unroll
-    for (int a = 0; a < E::k; ++a) nid[a] = g.bconn[a * g.blen + idx];
+    for (int a = 0; a < E::k; ++a) nid[a] = sched_load<STREAM>(&g.bconn[a * g.blen + idx]);
     const uint32_t *op = reinterpret_cast<const uint32_t *>(g.boff + static_cast<int64_t>(idx) * L::KKP);
 #pragma unroll
-    for (int w = 0; w < L::KW; ++w) ow[w] = op[w];
+    for (int w = 0; w < L::KW; ++w) ow[w] = sched_load<STREAM>(&op[w]);
     const uint32_t *np = g.bnode + static_cast<int64_t>(idx) * E::k;
 #pragma unroll
-    for (int a = 0; a < E::k; ++a) nw[a] = np[a];
+    for (int a = 0; a < E::k; ++a) nw[a] = sched_load<STREAM>(&np[a]);
 }
 
 // this thread's first element of the block and its first ordered-entry record
-template <class E>
+template <class E, bool STREAM = false>
 __device__ __forceinline__ void side_load_first(const BlockArgs &g, SideBlock<E> &s)
 {
     const int32_t tid = threadIdx.x;
-    if (s.e0 + tid < s.e1) side_load_elem<E>(g, s.e0 + tid, s.nid, s.ow, s.nw);
+    if (s.e0 + tid < s.e1) side_load_elem<E, STREAM>(g, s.e0 + tid, s.nid, s.ow, s.nw);
     s.ord0 = 0;
     s.ord1 = 0;
     if (s.o0 + tid < s.o1) {
-        s.ord0 = g.bord[2 * static_cast<int64_t>(s.o0 + tid)];
-        s.ord1 = g.bord[2 * static_cast<int64_t>(s.o0 + tid) + 1];
+        s.ord0 = sched_load<STREAM>(&g.bord[2 * static_cast<int64_t>(s.o0 + tid)]);
+        s.ord1 = sched_load<STREAM>(&g.bord[2 * static_cast<int64_t>(s.o0 + tid) + 1]);
     }
 }
 
@@ -322,7 +332,7 @@ __device__ __forceinline__ int side_element(const BlockArgs &g, int nloc, const 
 // number of degenerate quadrature points met.  With MULTI, elements beyond the
 // first NT of the list are loaded here, with their own registers; without it
 // the block must hold at most NT elements.
-template <class E, int Q, int NM, bool HA, int CF, int NT, bool MULTI>
+template <class E, int Q, int NM, bool HA, int CF, int NT, bool MULTI, bool STREAM = false>
 __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
                                             int rs)
 {
@@ -336,7 +346,7 @@ __device__ __forceinline__ int side_compute(const BlockArgs &g, const SideBlock<
             int32_t nid[E::k];
             uint32_t ow[SideLayout<E>::KW], nw[E::k];
             double x[E::n][E::k];
-            side_load_elem<E>(g, idx, nid, ow, nw);
+            side_load_elem<E, STREAM>(g, idx, nid, ow, nw);
             gather_coords<E>(nid, g.coords, g.N, x);
             bad += side_element<E, Q, NM, HA, CF>(g, s.nloc, nid, x, ow, nw, lds, dump, rs);
         }
@@ -406,12 +416,14 @@ __device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nlo
 // one block whose record, first elements and coordinates are loaded (or in
 // flight) in s.  LDS value entries must be all zero on entry (and no thread
 // may still be writing out a previous block) and are all zero on return.
+// Used by the batched kernel: further element chunks stream their schedule
+// words.
 template <class E, int Q, int NM, bool HA, int CF, int NT>
 __device__ __forceinline__ void side_block(const BlockArgs &g, const SideBlock<E> &s, double *lds, int32_t dump,
                                            int rs)
 {
     constexpr int NMAT = NM + (HA ? 1 : 0);
-    const int bad = side_compute<E, Q, NM, HA, CF, NT, true>(g, s, lds, dump, rs);
+    const int bad = side_compute<E, Q, NM, HA, CF, NT, true, true>(g, s, lds, dump, rs);
     if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
     __syncthreads();
     side_reduce<E, NMAT, NT>(g, s, lds, rs);
