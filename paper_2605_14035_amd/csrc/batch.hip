@@ -263,7 +263,7 @@ void autotune_batch(lfem_batch_s &b, hipStream_t s)
     float best = 1e30f;
     int best_cap = 4096;
     try {
-        const int caps[] = {2048, 3072, 4096, 4864};
+        const int caps[] = {2048, 3072, 4096, 4864, 4992};
         for (int cap : caps) {
             rebuild_all(b, cap, s);
             bool ok = true;
