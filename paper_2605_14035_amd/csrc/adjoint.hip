@@ -297,8 +297,11 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T,
                 for (int c = 0; c < NCH; ++c) acc[c] += v[i][c];
             }
     }
+    // written once, not read again here: non-temporal stores keep the staged
+    // contributions that neighbouring nodes still gather in the caches (the
+    // staged reads themselves must stay cached: hinting them is far slower)
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) grad[c * N + r] = acc[c];
+    for (int c = 0; c < NCH; ++c) __builtin_nontemporal_store(acc[c], &grad[c * N + r]);
 }
 
 void gather(int64_t N, int64_t T, int n, const int32_t *ne_ptr, const int32_t *ne, const double *stage,
