@@ -16,6 +16,7 @@ Every function takes a mesh dict as produced by ``meshgen`` (keys
 
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -34,15 +35,39 @@ OK, EINVAL, ENOMEM, EDEGENERATE = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no vendor libraries), plus the
+    """Compile the oracle with gcc (-O3 for the baseline x86-64 target, so no
+    fused multiply-adds and no reassociation; no vendor libraries), plus the
     long-double build used as a finite-difference reference."""
     for path, extra in ((_LIB, []), (_LIB_LD, ["-DORACLE_LONG_DOUBLE"])):
         if force or not os.path.exists(path):
-            tmp = path + ".tmp"
-            subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp,
-                            _SRC, "-lm"], check=True)
-            os.replace(tmp, path)
+            _compile(path, extra)
     return _LIB
+
+
+def _compile(path, extra):
+    tmp = path + ".tmp"
+    subprocess.run(["gcc", "-O3", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp, _SRC, "-lm"],
+                   check=True)
+    os.replace(tmp, path)
+
+
+@contextlib.contextmanager
+def planted(define: str):
+    """Test hook: while active, every oracle call (double build) runs a build of
+    lfem_oracle.c with -D<define>, a mistake planted on purpose, so that a test
+    can show that a pin fails on it.  Built into a temporary directory."""
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, f"liboracle_{define}.so")
+        _compile(path, [f"-D{define}"])
+        saved = _libs.pop(False, None)
+        try:
+            _libs[False] = _declare(C.CDLL(path))
+            yield
+        finally:
+            _libs.pop(False, None)
+            if saved is not None:
+                _libs[False] = saved
 
 
 _libs = {}
@@ -54,29 +79,36 @@ def lib(long_double: bool = False):
         path = _LIB_LD if key else _LIB
         if not os.path.exists(path):
             build(force=False)
-        L = C.CDLL(path)
-        dp = C.POINTER(C.c_double)
-        ip = C.POINTER(C.c_int32)
-        lp = C.POINTER(C.c_int64)
-        up = C.POINTER(C.c_uint8)
-        i64 = C.c_int64
-        ci = C.c_int
-        L.oracle_basis.argtypes = [ci, ci, dp, dp, dp]
-        L.oracle_element_matrices.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci,
-                                              i64, i64, dp]
-        L.oracle_assemble.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci, up, i64,
-                                      lp, ip, dp, lp]
-        L.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, C.c_double,
-                                    dp, dp, C.c_double, dp]
-        L.oracle_shape_grad.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp,
-                                        C.c_double, dp, dp, C.c_double, dp]
-        L.oracle_load.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp]
-        L.oracle_kll.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, dp]
-        for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
-                  L.oracle_energy, L.oracle_shape_grad, L.oracle_load, L.oracle_kll):
-            f.restype = ci
-        _libs[key] = L
+        _libs[key] = _declare(C.CDLL(path))
     return _libs[key]
+
+
+def _declare(L):
+    """Argument and return types of the oracle's C functions."""
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    lp = C.POINTER(C.c_int64)
+    up = C.POINTER(C.c_uint8)
+    i64 = C.c_int64
+    ci = C.c_int
+    L.oracle_basis.argtypes = [ci, ci, dp, dp, dp]
+    L.oracle_element_matrices.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci,
+                                          i64, i64, dp]
+    L.oracle_assemble.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci, up, i64,
+                                  lp, ip, dp, lp]
+    L.oracle_energy.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, C.c_double,
+                                dp, dp, C.c_double, dp]
+    L.oracle_shape_grad.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp,
+                                    C.c_double, dp, dp, C.c_double, dp]
+    L.oracle_load.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp]
+    L.oracle_kll.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, dp, dp]
+    L.oracle_assemble_numeric.argtypes = [ci, ci, ci, ci, dp, dp, i64, dp, i64, ip, dp, ci, lp, ip,
+                                          dp]
+    for f in (L.oracle_basis, L.oracle_element_matrices, L.oracle_assemble,
+              L.oracle_energy, L.oracle_shape_grad, L.oracle_load, L.oracle_kll,
+              L.oracle_assemble_numeric):
+        f.restype = ci
+    return L
 
 
 def _ptr(a, ctype):
@@ -168,6 +200,21 @@ def assemble(mesh, kind: str, coef=None, rows=None, rule=None):
     _check(st, "assemble")
     n = int(nnz[0])
     return row_ptr, col_idx[:n].copy(), vals[:n].copy()
+
+
+def assemble_numeric(mesh, kind: str, pattern, coef=None, rule=None):
+    """Values of the global matrix in a prebuilt CSR pattern (row_ptr, col_idx)
+    of the same element array: element loop with the slot of each local entry
+    found by binary search in its row (no COO, no sort)."""
+    args, keep, N, T, k = _mesh_args(mesh, *(rule or (None, None)))
+    row_ptr = np.ascontiguousarray(pattern[0], dtype=np.int64)
+    col_idx = np.ascontiguousarray(pattern[1], dtype=np.int32)
+    coef = _f64(coef)
+    vals = np.zeros(max(int(row_ptr[-1]), 1))
+    st = lib().oracle_assemble_numeric(*args, _ptr(coef, C.c_double), KIND[kind], _ptr(row_ptr, C.c_int64),
+                                       _ptr(col_idx, C.c_int32), _ptr(vals, C.c_double))
+    _check(st, "assemble_numeric")
+    return vals[:int(row_ptr[-1])]
 
 
 def energy(mesh, u, v, alpha=1.0, w=None, z=None, beta=1.0, long_double=False):

@@ -331,6 +331,16 @@ static void gather(const etype *t, int64_t N, const double *coords, int64_t T,
     }
 }
 
+/* Test hook, never defined in the oracle proper: a build with
+ * -DORACLE_PLANTED_COEF_MISTAKE pairs the nodal coefficient of local node r
+ * with the basis function of node r + 1, so that the tests can show that
+ * their pins of the coefficient branch catch such a mistake. */
+#ifdef ORACLE_PLANTED_COEF_MISTAKE
+#define COEF_NODE(r, k) (((r) + 1) % (k))
+#else
+#define COEF_NODE(r, k) (r)
+#endif
+
 /* kind: 0 mass, 1 stiffness.  coef: nodal coefficient interpolated with the
    basis (c_h = sum_r c_r phi_r), or NULL for 1.  out: k*k row-major. */
 static int element_matrix(const etype *t, int64_t N, const double *coords, int64_t T,
@@ -348,7 +358,7 @@ static int element_matrix(const etype *t, int64_t N, const double *coords, int64
         if (point_geometry(t, x, q, phi, grad, &mu)) status = OR_EDEGENERATE;
         if (coef) {
             f = 0.0;
-            for (a = 0; a < k; a++) f += ce[a] * phi[a];
+            for (a = 0; a < k; a++) f += ce[COEF_NODE(a, k)] * phi[a];
         }
         wmu = t->qw[q] * mu * f;
         for (a = 0; a < k; a++)
@@ -497,6 +507,50 @@ int oracle_assemble(int surface, int d, int p, int Q, const double *qp, const do
     free(J);
     free(V);
     if (st) return st;
+    return bad ? OR_EDEGENERATE : OR_OK;
+}
+
+/*
+ * Numeric phase alone, into a CSR pattern built beforehand (the structural
+ * pattern of the same element array, as oracle_assemble returns it): vals is
+ * set to zero, then every element's local matrix is added entry by entry in
+ * element order, the slot of (i, j) found by binary search in row i.  The sums
+ * are those of oracle_assemble (element order per entry).  This is the CPU
+ * counterpart of assembling into a precomputed sparsity pattern, which the
+ * paper names as the way FEM packages avoid the sort (section 4.2).
+ * Returns OR_EINVAL if an element pair is missing from the pattern.
+ */
+int oracle_assemble_numeric(int surface, int d, int p, int Q, const double *qp,
+                            const double *qw, int64_t N, const double *coords, int64_t T,
+                            const int32_t *conn, const double *coef, int kind,
+                            const int64_t *row_ptr, const int32_t *col_idx, double *vals)
+{
+    etype t;
+    int st = make_type(&t, surface, d, p, Q, qp, qw), bad = 0;
+    int64_t e, s;
+    real loc[KMAX * KMAX];
+    if (st) return st;
+    for (s = 0; s < row_ptr[N]; s++) vals[s] = 0.0;
+    for (e = 0; e < T; e++) {
+        int a, b;
+        if (element_matrix(&t, N, coords, T, conn, coef, kind, e, loc)) bad = 1;
+        for (a = 0; a < t.k; a++) {
+            int32_t gi = conn[(int64_t)a * T + e];
+            for (b = 0; b < t.k; b++) {
+                int32_t gj = conn[(int64_t)b * T + e];
+                int64_t lo = row_ptr[gi], hi = row_ptr[gi + 1];
+                while (lo < hi) {
+                    int64_t mid = lo + (hi - lo) / 2;
+                    if (col_idx[mid] < gj)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo >= row_ptr[gi + 1] || col_idx[lo] != gj) return OR_EINVAL;
+                vals[lo] = (double)((real)vals[lo] + loc[a * t.k + b]);
+            }
+        }
+    }
     return bad ? OR_EDEGENERATE : OR_OK;
 }
 

@@ -11,7 +11,10 @@ grad phi_j, evaluated with the same rule):
   with g in the tangent space (least squares on [DF^T ; nu^T]), nu taken
   from an SVD -- not the adjugate of L = [t1 t2 t1 x t2];
 * entries are computed one global pair (i, j) at a time, looping over the
-  elements that contain both nodes -- no COO, no sort.
+  elements that contain both nodes -- no COO, no sort;
+* with a nodal coefficient (weighted mass M_c, coefficient stiffness A_a)
+  the factor c_h(xi_q) = sum_r c_r phi_r(xi_q) is formed from the same
+  Vandermonde basis, per pair and point.
 """
 
 import itertools
@@ -57,7 +60,10 @@ def vandermonde_basis(d, p):
     return ev
 
 
-def brute(mesh):
+def brute(mesh, coef_c=None, coef_a=None):
+    """Entry-by-entry M (or M_c with the nodal coefficient coef_c) and A (or
+    A_a with coef_a); a nodal coefficient enters as c_h = sum_r c_r phi_r,
+    with phi_r the Vandermonde basis at the point."""
     d, p = mesh["dim"], mesh["order"]
     X = mesh["coords"].T
     F = mesh["conn"].T
@@ -100,8 +106,10 @@ def brute(mesh):
                     continue
                 b = bs[0]
                 for q, (phi, g, mu) in enumerate(geo[e]):
-                    m_ij += W[q] * mu * phi[a] * phi[b]
-                    a_ij += W[q] * mu * g[:, a] @ g[:, b]
+                    ch = 1.0 if coef_c is None else float(coef_c[F[e]] @ phi)
+                    ah = 1.0 if coef_a is None else float(coef_a[F[e]] @ phi)
+                    m_ij += W[q] * mu * ch * phi[a] * phi[b]
+                    a_ij += W[q] * mu * ah * g[:, a] @ g[:, b]
             Mb[(i, j)] = m_ij
             Ab[(i, j)] = a_ij
     return Mb, Ab
@@ -126,3 +134,35 @@ def test_entrywise_definition(t):
         scale = max(abs(v) for v in ref.values())
         for key, v in ref.items():
             assert abs(got[key] - v) <= 1e-13 * scale, (kind, key, got[key], v)
+
+
+@pytest.mark.parametrize("t", meshgen.ALL_TYPES)
+def test_entrywise_definition_with_coefficients(t):
+    """M_c and A_a (section 3.2 quadrature forms with the nodal coefficient
+    interpolated by the element basis) on the same tiny curved meshes."""
+    mesh = meshgen.small_mesh(*t, size=1)
+    T = min(mesh["conn"].shape[1], 6)
+    mesh = dict(mesh)
+    mesh["conn"] = np.ascontiguousarray(mesh["conn"][:, :T])
+    c, a = mesh["coef_c"], mesh["coef_a"]
+    Mb, Ab = brute(mesh, coef_c=c, coef_a=a)
+    check_against(mesh, Mb, Ab, c, a)
+
+
+def check_against(mesh, Mb, Ab, coef_c, coef_a):
+    """Largest scaled difference between the oracle's M_c, A_a and the
+    brute-force dictionaries (asserts the pattern agrees)."""
+    N = mesh["coords"].shape[1]
+    worst = 0.0
+    for kind, ref, coef in (("mass", Mb, coef_c), ("stiffness", Ab, coef_a)):
+        rp, ci, va = oracle.assemble(mesh, kind, coef=coef)
+        got = {}
+        for i in range(N):
+            for s in range(rp[i], rp[i + 1]):
+                got[(i, int(ci[s]))] = va[s]
+        assert set(got) == set(ref)
+        scale = max(abs(v) for v in ref.values())
+        worst = max(worst, max(abs(got[key] - v) for key, v in ref.items()) / scale)
+    assert worst <= 1e-13, worst
+    return worst
+

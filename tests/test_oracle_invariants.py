@@ -136,3 +136,16 @@ def test_nnz_kuhn_p2(n):
         row = ci[rp[i]:rp[i + 1]]
         assert np.all(np.diff(row) > 0)
         assert i in row
+
+
+@pytest.mark.parametrize("t", TYPES)
+def test_numeric_only_equals_coo_route(t):
+    """Assembling into the prebuilt pattern (slot by binary search) gives the
+    values of the COO + stable sort route: the same sums in the same (element)
+    order, so the same bits."""
+    mesh = meshgen.small_mesh(*t, size=3)
+    for kind, coef in (("mass", None), ("stiffness", None), ("mass", mesh["coef_c"]),
+                       ("stiffness", mesh["coef_a"])):
+        rp, ci, va = oracle.assemble(mesh, kind, coef=coef)
+        vn = oracle.assemble_numeric(mesh, kind, (rp, ci), coef=coef)
+        assert np.array_equal(vn, va), (kind, coef is not None)
