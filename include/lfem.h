@@ -104,8 +104,10 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * tetrahedra), with the weights summing to the reference measure.  Batched assembly takes the two default rules only.
  * Orders 3 and 4 take only the high-order rules (defaults: segment 5 points
  * for order 3 and 6 for order 4; triangle 16).
- * Builds the node -> element
- * incidence on the device (asynchronous on stream).
+ * Uploads the reference tables and builds the node -> element incidence
+ * asynchronously on stream (device buffers are allocated with hipMalloc
+ * first); use the handle on the same stream, or synchronise it before using
+ * the handle on another.
  * Errors: LFEM_EINVAL (sizes, nulls, n_elems * k >= 2^31),
  * LFEM_EUNSUPPORTED (type/rule), LFEM_ENOMEM, LFEM_EHIP.
  */
@@ -114,7 +116,9 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
                              int quad_points, void *stream, lfem_mesh_t *out);
 
 /* Point the mesh at new coordinates (moving mesh, same topology).  The next
- * assembly reads them; nothing is recomputed eagerly. */
+ * assembly reads them, also through a batch that holds the mesh (its next
+ * lfem_assemble_batch call re-uploads its descriptors); nothing is recomputed
+ * eagerly.  The new array must stay valid while the mesh may read it. */
 lfem_status lfem_mesh_set_coords(lfem_mesh_t m, const double *coords);
 
 /*
@@ -176,6 +180,20 @@ lfem_status lfem_assemble_weighted(lfem_mesh_t m, lfem_pattern_t p, const double
                                    double *vals, void *stream);
 
 /*
+ * Product of an assembled matrix with nvec nodal vectors:
+ *     y[c * N + i] = alpha * sum_j vals_ij x[c * N + j],   c < nvec,
+ * vals: nnz doubles on pattern p (any matrix this library assembled on it);
+ * x, y: nvec * N doubles, component-major, must not overlap.  Each row is
+ * summed in column order (bitwise reproducible).  The operation the
+ * paper's schemes apply to assembled matrices (the right-hand side M x^n of
+ * Dziuk's scheme, section 6.3), and the partial derivatives of
+ * u^T A v with respect to u and v (A v and A^T u = A u).
+ * Errors: LFEM_EINVAL (null pattern or buffers, nvec < 1, x == y), LFEM_EHIP.
+ */
+lfem_status lfem_spmv(lfem_pattern_t p, const double *vals, const double *x, double alpha, double *y,
+                      int nvec, void *stream);
+
+/*
  * Per-step system of the linearly implicit mean-curvature-flow scheme the
  * paper times against DUNE (section 6.3, Dziuk's algorithm):
  *     (M(x^n) + tau A(x^n)) x^{n+1} = M(x^n) x^n.
@@ -233,11 +251,14 @@ lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what
                                   int *variant_out);
 
 /*
- * Batched assembly: many meshes (curves, surfaces and planar domains of any
- * order and rule, uneven sizes) assembled in one persistent launch replayed
- * from a HIP graph.  what: matrices per mesh (LFEM_M | LFEM_A; coefficients
- * are not supported in batches).  Tetrahedral meshes: LFEM_EUNSUPPORTED.
- * autotune != 0 times the candidate launch shapes once at creation
+ * Batched assembly: many meshes of uneven size assembled in one persistent
+ * launch replayed from a HIP graph.  Covered: curves, surfaces and planar
+ * domains of order 1 or 2 under their two default rules (segment 2 or 3
+ * points, triangle 3 or 6 points), whose patterns carry a side-slot block
+ * schedule.  what: matrices per mesh (LFEM_M | LFEM_A; coefficients are not
+ * supported in batches).  Other meshes (tetrahedra, orders 3 and 4, the
+ * high-order rules): LFEM_EUNSUPPORTED.  autotune != 0 times the candidate
+ * block capacities once at creation and rebuilds the patterns' schedules
  * (SYNCHRONISES stream).  The handle keeps the mesh and pattern handles
  * (which must outlive it).
  */
@@ -247,9 +268,14 @@ lfem_status lfem_batch_create(int n, const lfem_mesh_t *meshes, const lfem_patte
 /*
  * Run the batch.  vals[i * nmat + j] is the output of matrix j of mesh i,
  * nmat = number of bits in `what`, ordered M then A; each has that mesh's
- * nnz doubles and is overwritten.  When the pointer set differs from the
- * previous call the library waits for the previous call to finish before
- * updating its device-side pointer table.
+ * nnz doubles and is overwritten.  Each call reads every mesh's current
+ * coordinates (lfem_mesh_set_coords).  When the output or coordinate pointers
+ * differ from the previous call the library waits for the previous upload to
+ * finish before updating its device-side pointer table.  If a pattern's block
+ * schedule was rebuilt since the batch was set up (lfem_pattern_autotune,
+ * another batch's autotuning), the call SYNCHRONISES stream and rebuilds the
+ * batch's work list and graph first (LFEM_EUNSUPPORTED if the new schedule
+ * is not one the batch kernel runs).
  */
 lfem_status lfem_assemble_batch(lfem_batch_t b, double *const *vals, void *stream);
 
@@ -314,7 +340,9 @@ lfem_status lfem_reference_table(int dim, int order, int quad_points, int *q_out
                                  double *w, double *xi, double *phi, double *dphi);
 
 /* Number of degenerate (element, quadrature point) evaluations seen by this
- * mesh since creation or the last reset.  SYNCHRONISES the device. */
+ * mesh since creation or the last reset.  SYNCHRONISES the whole device
+ * (hipDeviceSynchronize: the counter may be written from any stream the mesh
+ * was used on), then reads the counter. */
 lfem_status lfem_status_get(lfem_mesh_t m, int64_t *n_degenerate);
 lfem_status lfem_status_reset(lfem_mesh_t m, void *stream);
 
@@ -324,6 +352,9 @@ const char *lfem_last_error(void);
 /* Library version string. */
 const char *lfem_version(void);
 
+/* Release a handle and its device buffers.  Each destroy call first waits
+ * for all work on the device (hipDeviceSynchronize), since work on any stream
+ * may still read the buffers.  NULL is ignored. */
 void lfem_mesh_destroy(lfem_mesh_t m);
 void lfem_pattern_destroy(lfem_pattern_t p);
 void lfem_batch_destroy(lfem_batch_t b);

@@ -29,7 +29,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -190,6 +190,12 @@ def lfem_assemble_load(mesh, coef_f, b, stream=None):
     _lib.check(st, "lfem_assemble_load")
 
 
+def lfem_spmv(pattern, vals, x, alpha, y, nvec: int = 1, stream=None):
+    st = _L.lfem_spmv(pattern, _ptr(vals, torch.float64, "vals"), _ptr(x, torch.float64, "x"), float(alpha),
+                      _ptr(y, torch.float64, "y"), int(nvec), _stream(stream))
+    _lib.check(st, "lfem_spmv")
+
+
 def lfem_dziuk_system(mesh, pattern, tau, x, vals_m, vals_a, vals_s, rhs, stream=None):
     st = _L.lfem_dziuk_system(mesh, pattern, float(tau), _ptr(x, torch.float64, "x"),
                               _ptr(vals_m, torch.float64, "vals_m"), _ptr(vals_a, torch.float64, "vals_a"),
@@ -259,6 +265,6 @@ def lfem_batch_destroy(batch):
     _L.lfem_batch_destroy(batch)
 
 
-from .mesh import DeviceMesh, ShapeEnergy  # noqa: E402  (convenience wrappers)
+from .mesh import DeviceMesh, ShapeEnergy, assemble  # noqa: E402  (convenience wrappers)
 
-__all__ += ["DeviceMesh", "ShapeEnergy"]
+__all__ += ["DeviceMesh", "ShapeEnergy", "assemble"]

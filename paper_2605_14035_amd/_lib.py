@@ -40,7 +40,7 @@ EXPORTS = [
     "lfem_pattern_info",
     "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy",
 ]
 
@@ -88,6 +88,7 @@ def load():
     L.lfem_energy.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, vp, vp]
     L.lfem_assemble_load.argtypes = [vp, vp, vp, vp]
     L.lfem_assemble_kll.argtypes = [vp, vp, vp, vp, vp]
+    L.lfem_spmv.argtypes = [vp, vp, vp, dbl, vp, ci, vp]
     L.lfem_dziuk_system.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp]
     L.lfem_kll_system.argtypes = [vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.lfem_reference_table.argtypes = [ci, ci, ci, C.POINTER(ci), C.POINTER(ci), vp, vp, vp, vp]

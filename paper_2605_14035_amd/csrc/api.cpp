@@ -148,20 +148,22 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
             m->coords = coords;
             m->conn = conn;
             LFEM_HIP(hipGetDevice(&m->device));
-            m->host_tab = tab;
-            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->tab), tab.data.size() * sizeof(double)));
+            // the uploads read the mesh's own copy of the tables, which lives
+            // as long as the handle, so nothing here waits for the stream
+            m->host_tab = std::move(tab);
+            const RefTable &ht = m->host_tab;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->tab), ht.data.size() * sizeof(double)));
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->flags), 4 * sizeof(int32_t)));
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->degenerate), sizeof(unsigned long long)));
-            LFEM_HIP(hipMemcpyAsync(m->tab, tab.data.data(), tab.data.size() * sizeof(double),
+            LFEM_HIP(hipMemcpyAsync(m->tab, ht.data.data(), ht.data.size() * sizeof(double),
                                     hipMemcpyHostToDevice, S(stream)));
-            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->tabp), tab.pairs.size() * sizeof(double)));
-            LFEM_HIP(hipMemcpyAsync(m->tabp, tab.pairs.data(), tab.pairs.size() * sizeof(double),
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&m->tabp), ht.pairs.size() * sizeof(double)));
+            LFEM_HIP(hipMemcpyAsync(m->tabp, ht.pairs.data(), ht.pairs.size() * sizeof(double),
                                     hipMemcpyHostToDevice, S(stream)));
             LFEM_HIP(hipMemsetAsync(m->degenerate, 0, sizeof(unsigned long long), S(stream)));
             build_incidence(*m, S(stream));
-            // the host table must outlive the asynchronous copy
-            LFEM_HIP(hipStreamSynchronize(S(stream)));
         } catch (...) {
+            (void)hipStreamSynchronize(S(stream));
             release_mesh(*m);
             delete m;
             throw;
@@ -281,6 +283,20 @@ lfem_status lfem_kll_system(lfem_mesh_t m, lfem_pattern_t p, double tau, double 
         int variant = p->tuned_variant;
         if (variant == LFEM_SCATTER_BLOCKED && p->sched.nb == 0 && m->T > 0) variant = LFEM_SCATTER_STAGED;
         launch_kll_system(*m, *p, tau, delta0, nu, H, hist, vals_m, vals_a, vals_s, f, rhs, variant, S(stream));
+    });
+}
+
+lfem_status lfem_spmv(lfem_pattern_t p, const double *vals, const double *x, double alpha, double *y,
+                      int nvec, void *stream)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(p, LFEM_EINVAL, "null pattern");
+        LFEM_REQUIRE(nvec >= 1, LFEM_EINVAL, "nvec must be at least 1");
+        const int64_t n = p->mesh->N;
+        LFEM_REQUIRE(n == 0 || (x && y), LFEM_EINVAL, "x or y is null");
+        LFEM_REQUIRE(p->nnz == 0 || vals, LFEM_EINVAL, "vals is null");
+        LFEM_REQUIRE(x != y || n == 0, LFEM_EINVAL, "x and y must not alias");
+        launch_spmv(*p, vals, x, alpha, y, nvec, S(stream));
     });
 }
 

@@ -42,6 +42,8 @@ struct lfem_batch_s {
     hipEvent_t upload_done = nullptr;
     bool uploaded = false;
     std::vector<double *> last_vals;
+    std::vector<const double *> last_coords;
+    std::vector<uint64_t> gens;  // schedule generation of each pattern at prepare()
     int cap = 0;
 };
 
@@ -198,17 +200,26 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     LFEM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
     b.uploaded = false;
     b.last_vals.clear();
+    b.last_coords.clear();
+    b.gens.resize(b.n);
+    for (int i = 0; i < b.n; ++i) b.gens[i] = b.pats[i]->sched_gen;
     (void)s;
 }
 
+// The descriptor table holds the output pointers and each mesh's current
+// coordinate pointer (lfem_mesh_set_coords may have moved it); it is rewritten
+// when either set differs from the last upload.
 void upload_descriptors(lfem_batch_s &b, double *const *vals, hipStream_t s)
 {
     std::vector<double *> cur(vals, vals + static_cast<size_t>(b.n) * b.nmat);
-    if (b.uploaded && cur == b.last_vals) return;
+    std::vector<const double *> xs(b.n);
+    for (int i = 0; i < b.n; ++i) xs[i] = b.meshes[i]->coords;
+    if (b.uploaded && cur == b.last_vals && xs == b.last_coords) return;
     // the staging buffer may still feed the previous upload
     if (b.uploaded) LFEM_HIP(hipEventSynchronize(b.upload_done));
     for (int i = 0; i < b.n; ++i) {
         BlockArgs g = b.host_desc[i];
+        g.coords = xs[i];
         g.v[0] = g.v[1] = g.v[2] = nullptr;
         for (int j = 0; j < b.nmat; ++j) g.v[j] = cur[static_cast<size_t>(i) * b.nmat + j];
         b.pinned[i] = g;
@@ -216,6 +227,7 @@ void upload_descriptors(lfem_batch_s &b, double *const *vals, hipStream_t s)
     LFEM_HIP(hipMemcpyAsync(b.desc, b.pinned, sizeof(BlockArgs) * b.n, hipMemcpyHostToDevice, s));
     LFEM_HIP(hipEventRecord(b.upload_done, s));
     b.last_vals = cur;
+    b.last_coords = xs;
     b.uploaded = true;
 }
 
@@ -328,6 +340,20 @@ void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s)
         for (int j = 0; j < b->nmat; ++j)
             LFEM_REQUIRE(vals[static_cast<size_t>(i) * b->nmat + j] || b->pats[i]->nnz == 0,
                          LFEM_EINVAL, "null output in batch");
+    // a pattern whose block schedule was rebuilt since the graph was captured
+    // (lfem_pattern_autotune, another batch's tuning) has freed the schedule the
+    // descriptors point at: wait for earlier replays, then rebuild the work
+    // list, descriptors and graph from the current schedules
+    bool stale = false;
+    for (int i = 0; i < b->n; ++i) stale = stale || b->pats[i]->sched_gen != b->gens[i];
+    if (stale) {
+        LFEM_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < b->n; ++i)
+            LFEM_REQUIRE(batch_eligible(*b->meshes[i], *b->pats[i]), LFEM_EUNSUPPORTED,
+                         "a pattern of the batch was rescheduled into a form the batch kernel "
+                         "does not run (colour mode or staged only)");
+        prepare(*b, s);
+    }
     upload_descriptors(*b, vals, s);
     LFEM_HIP(hipGraphLaunch(b->exec, s));
 }

@@ -175,6 +175,7 @@ struct Pattern {
     size_t stage_bytes = 0;
     // blocked scatter
     BlockSchedule sched;
+    uint64_t sched_gen = 0;    // incremented by every schedule (re)build
     // host copies kept for rebuilding the schedule
     std::vector<int32_t> h_row_ptr, h_ne_ptr, h_ne, h_conn;
     int tuned_variant = LFEM_SCATTER_BLOCKED;
@@ -232,6 +233,8 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
 double *mesh_scratch(Mesh &m, size_t bytes);
 void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
 void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s);
+void launch_spmv(const Pattern &p, const double *vals, const double *x, double alpha, double *y, int nvec,
+                 hipStream_t s);
 void launch_dziuk(Mesh &m, Pattern &p, double tau, const double *x, double *vals_m, double *vals_a,
                   double *vals_s, double *rhs, int variant, hipStream_t s);
 void launch_kll_system(Mesh &m, Pattern &p, double tau, double delta0, const double *nu, const double *H,

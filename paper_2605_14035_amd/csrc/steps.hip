@@ -15,6 +15,8 @@
 // allocates once the pattern's and the mesh's lazy structures exist, so a
 // whole step can be captured in a HIP graph and replayed as the mesh moves
 // in place.
+#include <algorithm>
+
 #include "lfem_internal.hpp"
 
 namespace lfem {
@@ -68,7 +70,50 @@ void step_rows(int nc, const Mesh &m, const Pattern &p, const double *vm, const 
     LFEM_HIP(hipGetLastError());
 }
 
+// one thread per row and component block: y[c N + r] = alpha sum_j v_rj x[c N + j]
+// for c < NC, the sum in column order (bitwise reproducible)
+template <int NC>
+__global__ __launch_bounds__(256) void k_spmv(int64_t n_rows, const int32_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ col, const double *__restrict__ v,
+                                              const double *__restrict__ x, double alpha, double *__restrict__ y)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    const int32_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+        const double a = v[k];
+        const int64_t j = col[k];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = fma(a, x[c * n_rows + j], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) y[c * n_rows + r] = alpha * acc[c];
+}
+
 }  // namespace
+
+void launch_spmv(const Pattern &p, const double *vals, const double *x, double alpha, double *y, int nvec,
+                 hipStream_t s)
+{
+    const int64_t n = p.mesh->N;
+    if (n == 0) return;
+    const unsigned grid = static_cast<unsigned>((n + 255) / 256);
+    for (int c0 = 0; c0 < nvec; c0 += 4) {
+        const int nc = std::min(4, nvec - c0);
+        const double *xc = x + c0 * n;
+        double *yc = y + c0 * n;
+        switch (nc) {
+        case 1: k_spmv<1><<<grid, 256, 0, s>>>(n, p.row_ptr, p.col_idx, vals, xc, alpha, yc); break;
+        case 2: k_spmv<2><<<grid, 256, 0, s>>>(n, p.row_ptr, p.col_idx, vals, xc, alpha, yc); break;
+        case 3: k_spmv<3><<<grid, 256, 0, s>>>(n, p.row_ptr, p.col_idx, vals, xc, alpha, yc); break;
+        default: k_spmv<4><<<grid, 256, 0, s>>>(n, p.row_ptr, p.col_idx, vals, xc, alpha, yc); break;
+        }
+        LFEM_HIP(hipGetLastError());
+    }
+}
 
 void launch_dziuk(Mesh &m, Pattern &p, double tau, const double *x, double *vals_m, double *vals_a,
                   double *vals_s, double *rhs, int variant, hipStream_t s)

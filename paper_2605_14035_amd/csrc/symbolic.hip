@@ -556,6 +556,7 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
     LFEM_REQUIRE(max_rows >= 1 && max_rows <= kBlockMaxRows, LFEM_EINVAL, "rows per block out of range");
     LFEM_REQUIRE(m.p <= 2, LFEM_EUNSUPPORTED, "block schedules cover orders 1 and 2");
     free_schedule(p.sched);
+    ++p.sched_gen;
     BlockSchedule &b = p.sched;
     b.cap = cap;
     LFEM_REQUIRE(p.max_row <= cap, LFEM_EINVAL, "block capacity below the longest row");

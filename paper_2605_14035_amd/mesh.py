@@ -11,7 +11,7 @@ from . import (LFEM_A, LFEM_BULK, LFEM_M, LFEM_MC, LFEM_SCATTER_AUTO, LFEM_SURFA
                copy_from_device, lfem_assemble, lfem_assemble_kll, lfem_assemble_load,
                lfem_dziuk_system, lfem_energy, lfem_kll_system, lfem_mesh_create, lfem_mesh_destroy,
                lfem_mesh_set_coords, lfem_pattern_build,
-               lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_status_get)
+               lfem_pattern_destroy, lfem_pattern_get, lfem_shape_grad, lfem_spmv, lfem_status_get)
 
 
 class DeviceMesh:
@@ -55,14 +55,34 @@ class DeviceMesh:
         return self.pattern
 
     def pattern_tensors(self):
-        """(row_ptr int32 (N+1,), col_idx int32 (nnz,)) copied out of the pattern."""
+        """(row_ptr int32 (N+1,), col_idx int32 (nnz,)) copied out of the pattern
+        once and kept (the pattern is fixed for the handle's lifetime)."""
         self.build_pattern()
-        n, nnz, rp, ci = lfem_pattern_get(self.pattern)
-        row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.coords.device)
-        col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.coords.device)
-        copy_from_device(row_ptr, rp, (n + 1) * 4)
-        copy_from_device(col_idx, ci, nnz * 4)
-        return row_ptr, col_idx[:nnz]
+        if getattr(self, "_pattern_t", None) is None:
+            n, nnz, rp, ci = lfem_pattern_get(self.pattern)
+            row_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.coords.device)
+            col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.coords.device)
+            copy_from_device(row_ptr, rp, (n + 1) * 4)
+            copy_from_device(col_idx, ci, nnz * 4)
+            self._pattern_t = (row_ptr, col_idx[:nnz])
+        return self._pattern_t
+
+    def sparse_csr(self, vals):
+        """A torch.sparse_csr_tensor (N, N) over the pattern's index tensors
+        (shared between the matrices of this mesh) with the given (nnz,) values."""
+        rp, ci = self.pattern_tensors()
+        return torch.sparse_csr_tensor(rp, ci, vals, size=(self.N, self.N), dtype=torch.float64,
+                                       device=vals.device)
+
+    def matvec(self, vals, x, alpha=1.0, out=None, stream=None):
+        """y = alpha * V x for an assembled matrix with values `vals` (nnz,) and
+        x of shape (N,) or (n, N) (component-major); rows summed in column order."""
+        self.build_pattern(stream)
+        x = x.contiguous()
+        y = out if out is not None else torch.empty_like(x)
+        nvec = 1 if x.dim() == 1 else x.shape[0]
+        lfem_spmv(self.pattern, vals, x, alpha, y, nvec, stream)
+        return y
 
     def set_coords(self, coords):
         coords = coords.contiguous()
@@ -152,27 +172,87 @@ class DeviceMesh:
             pass
 
 
+class _AtCoords:
+    """Point a DeviceMesh at other coordinates for the duration of a block and
+    restore its own afterwards (the handle never keeps a pointer into a tensor
+    the caller may free)."""
+
+    def __init__(self, mesh, x):
+        self.mesh, self.x = mesh, x
+
+    def __enter__(self):
+        self.saved = self.mesh.coords
+        self.mesh.set_coords(self.x)
+        return self.mesh
+
+    def __exit__(self, *exc):
+        self.mesh.set_coords(self.saved)
+        return False
+
+
 class ShapeEnergy(torch.autograd.Function):
     """J(x) = alpha u^T A(x) v + beta w^T M(x) z as a differentiable function of
-    the node coordinates x (n_amb, N).  Forward: lfem_energy; backward:
-    lfem_shape_grad.  Gradients with respect to u, v, w, z are not provided."""
+    the node coordinates x (n_amb, N) and of the nodal vectors u, v, w, z.
+
+    Forward: lfem_energy (matrix-free).  Backward: dJ/dx by lfem_shape_grad;
+    dJ/du = alpha A v, dJ/dv = alpha A u, dJ/dw = beta M z, dJ/dz = beta M w
+    (A and M symmetric) by assembling A(x), M(x) and lfem_spmv, only for the
+    inputs that require a gradient.  The mesh's own coordinates are restored
+    after each call."""
 
     @staticmethod
     def forward(ctx, x, mesh, u, v, w=None, z=None, alpha=1.0, beta=1.0):
         x = x.detach().contiguous()
-        mesh.set_coords(x)
         J = torch.empty(1, dtype=torch.float64, device=x.device)
-        lfem_energy(mesh.handle, u, v, alpha, w, z, beta, J)
+        with _AtCoords(mesh, x):
+            lfem_energy(mesh.handle, u, v, alpha, w, z, beta, J)
         ctx.mesh = mesh
-        ctx.args = (u, v, w, z, alpha, beta)
-        ctx.save_for_backward(x)
+        ctx.args = (alpha, beta)
+        ctx.save_for_backward(x, u, v, w, z)
         return J[0]
 
     @staticmethod
     def backward(ctx, gJ):
-        (x,) = ctx.saved_tensors
-        u, v, w, z, alpha, beta = ctx.args
-        ctx.mesh.set_coords(x)
-        g = torch.empty_like(x)
-        lfem_shape_grad(ctx.mesh.handle, u, v, alpha, w, z, beta, g)
-        return (g * gJ, None, None, None, None, None, None, None)
+        x, u, v, w, z = ctx.saved_tensors
+        alpha, beta = ctx.args
+        mesh = ctx.mesh
+        need = ctx.needs_input_grad
+        gx = gu = gv = gw = gz = None
+        with _AtCoords(mesh, x):
+            if need[0]:
+                g = torch.empty_like(x)
+                lfem_shape_grad(mesh.handle, u, v, alpha, w, z, beta, g)
+                gx = g * gJ
+            want_a = u is not None and v is not None and (need[2] or need[3])
+            want_m = w is not None and z is not None and (need[4] or need[5])
+            if want_a or want_m:
+                what = (LFEM_A if want_a else 0) | (LFEM_M if want_m else 0)
+                mats = mesh.assemble(what)
+                if want_a:
+                    if need[2]:
+                        gu = mesh.matvec(mats["A"], v.detach(), alpha) * gJ
+                    if need[3]:
+                        gv = mesh.matvec(mats["A"], u.detach(), alpha) * gJ
+                if want_m:
+                    if need[4]:
+                        gw = mesh.matvec(mats["M"], z.detach(), beta) * gJ
+                    if need[5]:
+                        gz = mesh.matvec(mats["M"], w.detach(), beta) * gJ
+        return (gx, None, gu, gv, gw, gz, None, None)
+
+
+_KINDS = {"mass": LFEM_M, "m": LFEM_M, "stiffness": LFEM_A, "a": LFEM_A, "weighted": LFEM_MC, "mc": LFEM_MC}
+
+
+def assemble(mesh, kind, coef=None, scatter=LFEM_SCATTER_AUTO, stream=None):
+    """One matrix of a DeviceMesh as a torch.sparse_csr_tensor (N, N), float64:
+    kind "mass" (M), "stiffness" (A, with the nodal coefficient `coef` inside
+    when given) or "weighted" (M_c, `coef` required).  The index tensors are
+    the mesh's pattern, shared by every matrix assembled on it."""
+    bit = _KINDS[kind.lower()]
+    if bit == LFEM_MC and coef is None:
+        raise ValueError("the weighted mass needs a nodal coefficient")
+    out = mesh.assemble(bit, coef_a=coef if bit == LFEM_A else None,
+                        coef_c=coef if bit == LFEM_MC else None, scatter=scatter, stream=stream)
+    key = {LFEM_M: "M", LFEM_A: "A", LFEM_MC: "MC"}[bit]
+    return mesh.sparse_csr(out[key])

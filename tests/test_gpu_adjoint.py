@@ -124,3 +124,38 @@ def test_autograd_function(lf):
     assert abs(J2.item() - oracle.energy(m2, m["u"], m["u"], 1.0, m["v"], m["v"], 1.0)) \
         <= 1e-12 * abs(J2.item())
     dm.close()
+
+
+def test_autograd_nodal_vectors_and_restore(lf):
+    """Gradients with respect to u, v, w, z (alpha A v, alpha A u, beta M z,
+    beta M w) against the oracle's matrices, and the mesh's own coordinates
+    restored after forward and backward."""
+    import scipy.sparse as sp
+    m = meshgen.small_mesh("surface", 2, 2, size=3)
+    N = m["coords"].shape[1]
+    dm = lf.DeviceMesh.from_dict(m)
+    own = dm.coords
+    u, v, w, z = (cuda(m[k]).requires_grad_(True) for k in ("u", "v", "coef_c", "coef_a"))
+    x = (dm.coords * 1.05).clone().requires_grad_(True)
+    J = lf.ShapeEnergy.apply(x, dm, u, v, w, z, 0.7, -1.2)
+    assert dm.coords is own
+    gx, gu, gv, gw, gz = torch.autograd.grad(2.0 * J, (x, u, v, w, z))
+    assert dm.coords is own
+    mx = dict(m)
+    mx["coords"] = m["coords"] * 1.05
+    rp, ci, va = oracle.assemble(mx, "stiffness")
+    A = sp.csr_matrix((va, ci, rp), shape=(N, N))
+    rp, ci, va = oracle.assemble(mx, "mass")
+    M = sp.csr_matrix((va, ci, rp), shape=(N, N))
+    for got, ref in ((gu, 2 * 0.7 * (A @ m["v"])), (gv, 2 * 0.7 * (A @ m["u"])),
+                     (gw, 2 * -1.2 * (M @ m["coef_a"])), (gz, 2 * -1.2 * (M @ m["coef_c"]))):
+        assert np.linalg.norm(got.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    gref = oracle.shape_grad(mx, m["u"], m["v"], 0.7, m["coef_c"], m["coef_a"], -1.2)
+    assert np.linalg.norm(gx.cpu().numpy() - 2 * gref) <= 1e-12 * np.linalg.norm(2 * gref)
+    # the handle reads the mesh's own coordinates again
+    rp, ci = (t.cpu().numpy() for t in dm.pattern_tensors())
+    got = dm.assemble(lf.LFEM_M)["M"].cpu().numpy()
+    from gpu_util import assert_csr_close
+    assert_csr_close(rp, ci, got, oracle.assemble(m, "mass"), what="mass after ShapeEnergy")
+    dm.close()
+

@@ -123,3 +123,60 @@ def test_batch_edge_cases(lf):
     assert ei.value.status == 6
     for x in (d, de, dt):
         x.close()
+
+
+def test_batch_follows_moved_coordinates(lf):
+    """lfem_mesh_set_coords on a batched mesh: the next batch call assembles at
+    the new coordinates (a new tensor, the old one released)."""
+    ms = mixed_meshes()
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w)
+    i = len(dms) - 1  # the frequency-16 P2 sphere
+    moved = dict(ms[i])
+    moved["coords"] = ms[i]["coords"] * 0.7
+    dms[i].set_coords(torch.as_tensor(moved["coords"], device="cuda"))
+    torch.cuda.empty_cache()
+    lf.lfem_assemble_batch(b, vals)
+    torch.cuda.synchronize()
+    rp, ci = (x.cpu().numpy() for x in dms[i].pattern_tensors())
+    for j, kind in enumerate(("mass", "stiffness")):
+        assert_csr_close(rp, ci, vals[2 * i + j][:dms[i].nnz].cpu().numpy(), oracle.assemble(moved, kind),
+                         what=f"moved mesh {kind}")
+    # the unmoved meshes are unchanged
+    for k, d in enumerate(dms[:-1]):
+        single = d.assemble(w, scatter=lf.LFEM_SCATTER_BLOCKED)
+        assert torch.equal(vals[2 * k][:d.nnz], single["M"])
+        assert torch.equal(vals[2 * k + 1][:d.nnz], single["A"])
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+
+
+def test_batch_after_pattern_retuned(lf):
+    """A pattern's schedule rebuilt after the batch was created (autotuning the
+    pattern): the batch rebuilds its work list and still matches per-mesh
+    launches with the new schedules bitwise, and the oracle."""
+    ms = mixed_meshes()
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w)
+    for d in dms[-2:]:
+        lf.lfem_pattern_autotune(d.handle, d.pattern, w)
+    vals2 = [torch.full_like(v, float("nan")) for v in vals]
+    lf.lfem_assemble_batch(b, vals2)
+    torch.cuda.synchronize()
+    for i, (m, d) in enumerate(zip(ms, dms)):
+        single = d.assemble(w, scatter=lf.LFEM_SCATTER_BLOCKED)
+        assert torch.equal(vals2[2 * i][:d.nnz], single["M"]), i
+        assert torch.equal(vals2[2 * i + 1][:d.nnz], single["A"]), i
+        rp, ci = (x.cpu().numpy() for x in d.pattern_tensors())
+        assert_csr_close(rp, ci, vals2[2 * i + 1][:d.nnz].cpu().numpy(), oracle.assemble(m, "stiffness"),
+                         what=f"retuned batch mesh {i}")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
