@@ -291,6 +291,24 @@ lfem_status lfem_shape_grad(lfem_mesh_t m, const double *u, const double *v, dou
                             const double *w, const double *z, double beta, double *grad,
                             void *stream);
 
+/*
+ * lfem_shape_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and result (bit for bit) as lfem_shape_grad, but
+ * the staged per-element contributions live in a fixed 32 MiB workspace
+ * inside the library (one per GPU, held until the process ends), so the
+ * call makes no hipMalloc / hipFree or other allocating call.  Limit:
+ * k * n_amb * n_elems <= 4194304 doubles (e.g. 233,016 P2 surface
+ * triangles); larger meshes get LFEM_ERANGE before anything is launched.
+ * The mesh's device must be current.  Calls on one GPU share the
+ * workspace: calls that overlap on one GPU (different streams, or other
+ * threads) race; serialise them.  Errors: LFEM_EINVAL (null mesh or grad,
+ * wrong current device), LFEM_ERANGE (mesh too large), LFEM_EHIP.
+ */
+lfem_status lfem_shape_grad_noalloc(lfem_mesh_t m, const double *u, const double *v, double alpha,
+                                    const double *w, const double *z, double beta, double *grad,
+                                    void *stream);
+
 /* Matrix-free value of the same J(x) into the device scalar *J_out. */
 lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double alpha,
                         const double *w, const double *z, double beta, double *J_out,

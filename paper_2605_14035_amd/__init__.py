@@ -29,7 +29,7 @@ __all__ = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -175,6 +175,14 @@ def lfem_shape_grad(mesh, u, v, alpha, w, z, beta, grad, stream=None):
                             _ptr(z, torch.float64, "z"), float(beta),
                             _ptr(grad, torch.float64, "grad"), _stream(stream))
     _lib.check(st, "lfem_shape_grad")
+
+
+def lfem_shape_grad_noalloc(mesh, u, v, alpha, w, z, beta, grad, stream=None):
+    st = _L.lfem_shape_grad_noalloc(mesh, _ptr(u, torch.float64, "u"), _ptr(v, torch.float64, "v"),
+                                    float(alpha), _ptr(w, torch.float64, "w"),
+                                    _ptr(z, torch.float64, "z"), float(beta),
+                                    _ptr(grad, torch.float64, "grad"), _stream(stream))
+    _lib.check(st, "lfem_shape_grad_noalloc")
 
 
 def lfem_energy(mesh, u, v, alpha, w, z, beta, J_out, stream=None):

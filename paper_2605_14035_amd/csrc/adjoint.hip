@@ -24,13 +24,44 @@
 // (the Frobenius norm of the tangential gradient: |J K g|^2 = g^T K g), are
 // staged and gathered the same way.
 #include <cmath>
+#include <mutex>
 
 #include "element.hpp"
 #include "lfem_internal.hpp"
 
 namespace lfem {
 
+// Fixed device workspace of the allocation-free shape gradient
+// (lfem_shape_grad_noalloc): the staged per-(element, local node) contributions,
+// k * n_amb * T doubles, at most kNoAllocScratchDoubles (32 MiB).  Every GPU the
+// library runs on holds one copy until the process ends.  In host code the
+// array's name is not a device address: kernels receive the per-device
+// address that noalloc_scratch() obtains with hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 22;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the address of `scratch` on the current device, looked up once per device
+double *noalloc_scratch(const Mesh &m)
+{
+    int dev = -1;
+    LFEM_HIP(hipGetDevice(&dev));
+    LFEM_REQUIRE(dev == m.device, LFEM_EINVAL, "the mesh's device must be the current device");
+    LFEM_REQUIRE(dev >= 0 && dev < kMaxDevices, LFEM_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        LFEM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        LFEM_REQUIRE(ptr, LFEM_EHIP, "hipGetSymbolAddress returned no address for the workspace");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
 
 // GRAD = false: per-element energy into out[e]
 // GRAD = true:  per (local node a, component c) contributions into out[(a*T + e)*n + c]
@@ -496,6 +527,22 @@ void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
 {
     const size_t cnt = static_cast<size_t>(m.k) * m.namb * m.T;
     double *stage = mesh_scratch(m, std::max<size_t>(cnt, 1) * sizeof(double));
+    dispatch(m, true, u, v, alpha, w, z, beta, stage, s);
+    gather(m.N, m.T, m.namb, m.ne_ptr, m.ne, stage, grad, s);
+}
+
+// The same kernels as launch_shape_grad with the staging in the fixed
+// workspace.  Every staged entry the gather reads is written by this call's
+// k_adjoint first, so nothing needs clearing; calls that overlap on one GPU
+// share the workspace and race.
+void launch_shape_grad_noalloc(Mesh &m, const double *u, const double *v, double alpha, const double *w,
+                               const double *z, double beta, double *grad, hipStream_t s)
+{
+    const size_t cnt = static_cast<size_t>(m.k) * m.namb * m.T;
+    LFEM_REQUIRE(cnt <= kNoAllocScratchDoubles, LFEM_ERANGE,
+                 "mesh too large for the fixed workspace of lfem_shape_grad_noalloc "
+                 "(k * n_amb * n_elems must not exceed 4194304)");
+    double *stage = noalloc_scratch(m);
     dispatch(m, true, u, v, alpha, w, z, beta, stage, s);
     gather(m.N, m.T, m.namb, m.ne_ptr, m.ne, stage, grad, s);
 }

@@ -369,6 +369,16 @@ lfem_status lfem_shape_grad(lfem_mesh_t m, const double *u, const double *v, dou
     });
 }
 
+lfem_status lfem_shape_grad_noalloc(lfem_mesh_t m, const double *u, const double *v, double alpha,
+                                    const double *w, const double *z, double beta, double *grad,
+                                    void *stream)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(m && grad, LFEM_EINVAL, "null mesh or grad");
+        launch_shape_grad_noalloc(*m, u, v, alpha, w, z, beta, grad, S(stream));
+    });
+}
+
 lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double alpha,
                         const double *w, const double *z, double beta, double *J_out,
                         void *stream)

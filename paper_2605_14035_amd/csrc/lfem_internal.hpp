@@ -230,6 +230,8 @@ void launch_energy(Mesh &m, const double *u, const double *v, double alpha, cons
 void launch_shape_grad(Mesh &m, const double *u, const double *v, double alpha,
                        const double *w, const double *z, double beta, double *grad,
                        hipStream_t s);
+void launch_shape_grad_noalloc(Mesh &m, const double *u, const double *v, double alpha, const double *w,
+                               const double *z, double beta, double *grad, hipStream_t s);
 double *mesh_scratch(Mesh &m, size_t bytes);
 void launch_load(Mesh &m, const double *f, double *b, hipStream_t s);
 void launch_kll(Mesh &m, const double *nu, const double *H, double *f, hipStream_t s);
