@@ -79,9 +79,22 @@ def cpu_baseline(mesh):
         oracle.element_matrices(mesh, "stiffness")
         loc.append(time.perf_counter() - t0)
     tl = statistics.median(loc)
+    # numeric-only, like for like with the GPU's numeric phase: M and A into the
+    # prebuilt pattern, each slot found by binary search in its row
+    rp, ci, _ = oracle.assemble(mesh, "mass")
+    num = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.assemble_numeric(mesh, "mass", (rp, ci))
+        oracle.assemble_numeric(mesh, "stiffness", (rp, ci))
+        num.append(time.perf_counter() - t0)
+    tn = statistics.median(num)
     return {"value": T / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"whole workload ({T} elements, M and A, COO + stable sort + CSR), "
                       f"median of 3 runs: {t:.2f} s",
+            "numeric_only": {"value": T / tn, "unit": "elements/s", "cores": 1, "seconds": tn,
+                             "sample": "the same M and A summed into the prebuilt CSR pattern "
+                                       "(binary-search slot lookup per row), median of 3 runs"},
             "local_matrices_only_elements_per_s": T / tl,
             "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
 
@@ -182,6 +195,16 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     import numpy as np
     rows = {}
     N, T = dm2.N, dm2.T
+    # the bench workload under the other two scatter variants (FP64 atomics into
+    # zeroed values, and the staged slot-sorted reduction)
+    oc = {k: torch.empty(dm2.nnz, dtype=torch.float64, device="cuda") for k in ("M", "A")}
+    for name, var in (("atomic", lf.LFEM_SCATTER_ATOMIC), ("staged", lf.LFEM_SCATTER_STAGED)):
+        rows[f"{name}_c2"] = row_entry(
+            f"M + A, P2 ellipsoid (655,360 elements), {name} scatter",
+            event_times(torch, lambda: lf.lfem_assemble(dm2.handle, dm2.pattern, lf.LFEM_M | lf.LFEM_A, None, None,
+                                                        oc["M"], oc["A"], None, var)),
+            T, 3 * N * 8 + 6 * T * 4 + 2 * dm2.nnz * 8, scatter=name)
+    del oc
     f = torch.as_tensor(mesh2["coef_c"], device="cuda")
     b = torch.empty(N, dtype=torch.float64, device="cuda")
     rows["load_c2"] = row_entry("load vector b = int f_h phi_j, P2 ellipsoid (655,360 elements)",
@@ -301,6 +324,15 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
             dd_bytes(dd, dom, Nd, Td, nnzd), nodes=Nd, nnz=nnzd, ns_per_element=ms[1] * 1e6 / Td,
             scatter={1: "blocked", 2: "staged", 3: "atomic"}[variant])
         dmd.close()
+    rows.update(tets_rows(lf, torch, meshgen))
+    return rows
+
+
+def tets_rows(lf, torch, meshgen, atomic=False):
+    """P2 tetrahedra, M + A_a on the 64^3 Kuhn cube: 11-point rule (and the
+    35-point degree-7 rule), each with its autotuned scatter; with `atomic`
+    also the FP64-atomic scatter under the 11-point rule."""
+    rows = {}
     m3 = meshgen.config3()
     dm3 = lf.DeviceMesh.from_dict(m3)
     dm3.build_pattern()
@@ -321,6 +353,12 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     t3 = rows["tets_c3"]["ms_mean"] * 1e-3
     rows["tets_c3"].update({"flops_per_element": flops_e, "tflops": flops_e * T3 / t3 / 1e12,
                             "frac_fp64_peak": flops_e * T3 / t3 / 78.6e12})
+    b3 = rows["tets_c3"]["alg_bytes"]
+    rows["tets_c3"]["roofline"] = {
+        "bound": "alu", "achieved": flops_e * T3 / t3 / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+        "frac": flops_e * T3 / t3 / 78.6e12, "traffic": None,
+        "hbm_achieved_GBs": b3 / t3 / 1e9, "hbm_frac": b3 / t3 / 1e9 / HBM_PEAK_GBS,
+        "alg_bytes_per_launch": b3, "flops_per_launch": flops_e * T3}
     dm3.close()
     # the same workload under the degree-7 tetrahedral rule (35 points), the degree the paper
     # integrates P2 tetrahedra with (section 5.2)
@@ -338,6 +376,16 @@ def other_rows(lf, torch, meshgen, mesh2, dm2):
     rows["tets_c3_degree7"].update({"flops_per_element": flops7, "tflops": flops7 * T3 / t7 / 1e12,
                                     "frac_fp64_peak": flops7 * T3 / t7 / 78.6e12})
     dm7.close()
+    if atomic:
+        dma = lf.DeviceMesh.from_dict(m3)
+        dma.build_pattern()
+        rows["tets_c3_atomic"] = row_entry(
+            "P2 tetrahedra M + A_a, 11-point rule, FP64-atomic scatter",
+            event_times(torch, lambda: lf.lfem_assemble(dma.handle, dma.pattern, lf.LFEM_M | lf.LFEM_A, ca, None,
+                                                        o3["M"], o3["A"], None, lf.LFEM_SCATTER_ATOMIC),
+                        reps=5, warm=1),
+            T3, 3 * N3 * 8 + 10 * T3 * 4 + N3 * 8 + 2 * nnz3 * 8, scatter="atomic", nnz=nnz3)
+        dma.close()
     return rows
 
 
@@ -351,6 +399,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the load / non-linear terms / shape gradient / tetrahedra measurements")
+    ap.add_argument("--only-tets", action="store_true",
+                    help="run only the P2 tetrahedra rows (64^3 Kuhn cube) and print them as one JSON "
+                         "line (for profiling that workload alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a 256 MiB device copy 3 times (a kernel of known traffic that "
                          "calibrates hardware byte counters)")
@@ -374,6 +425,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_tets:
+        print(json.dumps({"rows": tets_rows(lf, torch, meshgen, atomic=True)}))
+        return
     t0 = time.perf_counter()
     mesh = meshgen.config2()
     gen_s = time.perf_counter() - t0
@@ -438,6 +492,16 @@ def main():
         torch.cuda.synchronize()
         copies.append(a_ev.elapsed_time(b_ev))
     copy_gbs = 2 * dst.numel() * 8 / (statistics.median(copies) * 1e-3) / 1e9
+    # and a write-only stream of the same size (84 % of the c2 bytes are writes)
+    fills = []
+    for _ in range(10):
+        a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_ev.record(stream)
+        dst.fill_(1.0)
+        b_ev.record(stream)
+        torch.cuda.synchronize()
+        fills.append(a_ev.elapsed_time(b_ev))
+    fill_gbs = dst.numel() * 8 / (statistics.median(fills) * 1e-3) / 1e9
     del scrub, dst, src
     ms_per_step = wall * 1e3 / args.steps
     value = T / (ms_per_step * 1e-3)
@@ -477,6 +541,7 @@ def main():
             "kernel_ms_median_after_512MB_scrub": scrub_ms,
             "frac_after_512MB_scrub": b_alg / (scrub_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "copy_256MiB_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+            "write_256MiB_GBs": fill_gbs, "frac_of_write": achieved / fill_gbs,
             "kernel_source_digest": digest,
         },
         "pattern_build_s": pattern_s,

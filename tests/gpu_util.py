@@ -43,3 +43,23 @@ def assert_rows_close(rp, ci, got, ref_rows_csr, rows, tol=TOL, what=""):
         worst = max(worst, w)
     assert worst <= tol, f"{what}: row-scaled error {worst:.3e} > {tol}"
     return worst
+
+
+
+def grad_abs_scale(oracle, m, *args):
+    """Per node r the sum, over the elements containing r, of the largest
+    entry of that element's own shape-gradient contribution (each computed by
+    the oracle on the one-element mesh), broadcast over the components: the
+    scale of the rounding error of the summed gradient,
+    |fl(sum_e g_e) - sum_e g_e| <= c eps sum_e |g_e|.  Gradient entries cancel
+    between elements (interior nodes of flat meshes nearly balance), so the
+    largest entry of the whole gradient is not the right scale for them; the
+    element's largest entry (like the row maximum of a matrix) is."""
+    n, N = m["coords"].shape
+    S = np.zeros(N)
+    T = m["conn"].shape[1]
+    for e in range(T):
+        one = dict(m)
+        one["conn"] = np.ascontiguousarray(m["conn"][:, e:e + 1])
+        S[m["conn"][:, e]] += np.abs(oracle.shape_grad(one, *args)).max()
+    return np.broadcast_to(S, (n, N))

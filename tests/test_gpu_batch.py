@@ -180,3 +180,38 @@ def test_batch_after_pattern_retuned(lf):
     lf.lfem_batch_destroy(b)
     for d in dms:
         d.close()
+
+
+def test_config4_full_batch(lf):
+    """All 256 meshes of the batched workload (displaced geodesic spheres,
+    P1/P2 alternating, 11.4 M triangles), autotuned as the benchmark runs it:
+    every output bitwise equal to the per-mesh launch with the same schedule,
+    and a few meshes (the smallest P1 and P2, a mid-size P2) against the
+    oracle in full."""
+    ms = meshgen.config4()
+    print("config4: 256 meshes", flush=True)
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w, autotune=1)
+    print("config4: batch done, comparing with per-mesh launches", flush=True)
+    for i, d in enumerate(dms):
+        single = d.assemble(w, scatter=lf.LFEM_SCATTER_BLOCKED)
+        assert torch.equal(vals[2 * i][:d.nnz], single["M"]), i
+        assert torch.equal(vals[2 * i + 1][:d.nnz], single["A"]), i
+        del single
+    sizes = [d.T for d in dms]
+    p1 = [i for i in range(len(ms)) if ms[i]["order"] == 1]
+    p2 = [i for i in range(len(ms)) if ms[i]["order"] == 2]
+    picks = {min(p1, key=sizes.__getitem__), min(p2, key=sizes.__getitem__),
+             sorted(p2, key=sizes.__getitem__)[len(p2) // 2]}
+    for i in sorted(picks):
+        print(f"config4: oracle check mesh {i} ({sizes[i]} triangles, P{ms[i]['order']})", flush=True)
+        rp, ci = (x.cpu().numpy() for x in dms[i].pattern_tensors())
+        for j, kind in enumerate(("mass", "stiffness")):
+            assert_csr_close(rp, ci, vals[2 * i + j][:dms[i].nnz].cpu().numpy(), oracle.assemble(ms[i], kind),
+                             what=f"config4 mesh {i} {kind}")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()

@@ -266,16 +266,30 @@ def test_config3_small_full(lf, variant):
     dm.close()
 
 
-def test_config3_full_size_sampled(lf):
-    """64^3 Kuhn cube, 1,572,864 P2 tets: pattern size closed form, sampled
-    rows against the oracle, and the invariants 1^T M 1 = 1, A_a 1 = 0."""
-    m = meshgen.config3()
-    say("config3 full size")
+@pytest.fixture(scope="module")
+def c3():
+    return meshgen.config3()
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_config3_full_size_sampled(lf, c3, tuned):
+    """64^3 Kuhn cube, 1,572,864 P2 tets, 11-point rule, M and A_a in one call:
+    with the pattern's default scatter, and (tuned) in the launch the benchmark
+    row times (scatter and block size chosen by the autotuner).  Pattern size
+    closed form, sampled rows against the oracle, the invariants
+    1^T M 1 = 1 and A_a 1 = 0, and the same bits on a second call."""
+    m = c3
+    say(f"config3 full size, tuned={tuned}")
     dm = lf.DeviceMesh.from_dict(m)
     ca = torch.as_tensor(m["coef_a"], device="cuda")
     dm.build_pattern()
     assert dm.nnz == 60859905
+    if tuned:
+        say("  autotuned scatter:", lf.lfem_pattern_autotune(dm.handle, dm.pattern, lf.LFEM_M | lf.LFEM_A))
     out = dm.assemble(lf.LFEM_M | lf.LFEM_A, coef_a=ca)
+    again = dm.assemble(lf.LFEM_M | lf.LFEM_A, coef_a=ca)
+    assert torch.equal(out["M"], again["M"]) and torch.equal(out["A"], again["A"])
+    del again
     rp_t, ci_t = dm.pattern_tensors()
     rows_t = torch.repeat_interleave(torch.arange(dm.N, device="cuda"),
                                      (rp_t[1:] - rp_t[:-1]).long())
