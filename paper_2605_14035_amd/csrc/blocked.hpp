@@ -99,6 +99,101 @@ __device__ __forceinline__ int element_local(
     return bad;
 }
 
+// Local matrices of one element, mass-class outputs formed after the point
+// loop: the loop keeps only the stiffness accumulators in registers and
+// stores the per-point mass factors f_q = w_q mu_q c_h(xi_q) in this thread's
+// LDS column fl[(s * Q + q) * NT]; each mass value is then
+// M_ab = sum_q f_q phi_a phi_b (xi_q) from the pair-major table, handed to
+// put(p, mat, value) pair by pair with the stiffness value LA[p] (mat = NM).
+// Same sums as element_local, with about 2 * NM * np fewer live registers
+// through the point loop.
+template <class E, int Q, int NM, bool HA, int NT, class Put>
+__device__ __forceinline__ int element_local_put(
+    const int32_t (&nid)[E::k], const double (&x)[E::n][E::k], const double *__restrict__ tab,
+    const double *__restrict__ tabp, const double *__restrict__ cm0, const double *__restrict__ cm1,
+    const double *__restrict__ ca, double *fl, Put &&put)
+{
+    constexpr int PS = Q * (1 + E::nsym);  // pair-major table: Q mass values, then Q * nsym stiffness
+    double J0[E::n][E::d], H[E::n][E::nh > 0 ? E::nh : 1];
+    jacobian_setup<E>(x, J0, H);
+    double LA[E::np];
+#pragma unroll
+    for (int p = 0; p < E::np; ++p) LA[p] = 0.0;
+    const double *cms[2] = {cm0, cm1};
+    int bad = 0;
+    // one point per iteration, not unrolled: unrolling lets the table loads of
+    // every point be hoisted, which costs more registers than it saves
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        cdouble *t = const_table(tab) + q * E::stride;
+        double J[E::n][E::d];
+        jacobian_q<E>(x, J0, H, t, J);
+        double K[E::d][E::d], mu;
+        geometry<E>(J, K, mu);
+        bad += !(mu > 0.0 && mu < INFINITY);
+        const double wmu = t[0] * mu;
+#pragma unroll
+        for (int s = 0; s < NM; ++s) {
+            double fs = wmu;
+            if (cms[s]) {
+                double ch = 0.0;
+#pragma unroll
+                for (int a = 0; a < E::k; ++a) ch = fma(cms[s][nid[a]], t[E::off_phi + a], ch);
+                fs *= ch;
+            }
+            fl[(s * Q + q) * NT] = fs;
+        }
+        if constexpr (HA) {
+            double fa = wmu;
+            if (ca) {
+                double ah = 0.0;
+#pragma unroll
+                for (int a = 0; a < E::k; ++a) ah = fma(ca[nid[a]], t[E::off_phi + a], ah);
+                fa *= ah;
+            }
+#pragma unroll
+            for (int m = 0; m < E::d; ++m)
+#pragma unroll
+                for (int l = 0; l < E::d; ++l) K[m][l] *= fa;
+            // row a of the pairs: h_a = K g_a, then A_ab += h_a . g_b (only the
+            // current h_a is live)
+            int p = 0;
+#pragma unroll
+            for (int a = 0; a < E::k; ++a) {
+                double h[E::d];
+#pragma unroll
+                for (int m = 0; m < E::d; ++m) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int l = 0; l < E::d; ++l) acc = fma(K[m][l], t[E::off_g + a * E::d + l], acc);
+                    h[m] = acc;
+                }
+#pragma unroll
+                for (int b = a; b < E::k; ++b) {
+                    double acc = LA[p];
+#pragma unroll
+                    for (int m = 0; m < E::d; ++m) acc = fma(h[m], t[E::off_g + b * E::d + m], acc);
+                    LA[p] = acc;
+                    ++p;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < E::np; ++p) {
+        cdouble *tp = const_table(tabp) + p * PS;
+#pragma unroll
+        for (int s = 0; s < NM; ++s) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc = fma(fl[(s * Q + q) * NT], tp[q], acc);
+            put(p, s, acc);
+        }
+        if constexpr (HA) put(p, NM, LA[p]);
+    }
+    return bad;
+}
+
 template <int K>
 __host__ __device__ constexpr int pair_index(int a, int b)
 {

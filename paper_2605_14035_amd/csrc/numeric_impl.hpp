@@ -107,14 +107,22 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
 template <class E>
 constexpr bool stage_tab_lds() { return E::d <= 2 && E::p >= 3; }
 
-template <class E, int Q>
-constexpr size_t stage_lds_bytes() { return stage_tab_lds<E>() ? size_t(E::np) * Q * (1 + E::nsym) * sizeof(double) : 0; }
+// tetrahedra under rules of up to 11 points: the per-point mass factors of
+// each thread (NM * Q doubles)
+template <class E, int Q, int NM>
+constexpr size_t stage_lds_bytes()
+{
+    return stage_tab_lds<E>() ? size_t(E::np) * Q * (1 + E::nsym) * sizeof(double)
+                              : (E::d == 3 && Q <= 11 ? size_t(NM > 0 ? NM : 1) * Q * 256 * sizeof(double) : 0);
+}
 
 template <class E, int Q, int NM, bool HA>
-__global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                               double *__restrict__ stage)
+__device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const int32_t *__restrict__ conn,
+                                           double *__restrict__ stage)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous element ranges per XCD: neighbouring elements share nodes,
+    // whose coordinates then come from one L2
+    const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     constexpr bool TAB_LDS = stage_tab_lds<E>();
     const double *tabp = g.tabp;
     if constexpr (TAB_LDS) {
@@ -133,16 +141,28 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
     gather_coords<E>(nid, g.coords, g.N, x);
     if constexpr (E::d == 3) {
         // tetrahedra: the per-point data (7 doubles a point: 77 for 11 points,
-        // 245 for 35) outweighs the local matrices, so accumulate those point
-        // by point instead
-        double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
-        const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
-        if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+        // 245 for 35) outweighs the local stiffness matrix, so that one is
+        // accumulated point by point; the mass values are formed after the
+        // point loop from the Q per-point factors, which keeps their 55
+        // accumulators out of the loop's registers
+        double *out = stage + e * E::np * NMAT;
+        if constexpr (Q <= 11) {
+            extern __shared__ double fl_lds[];
+            const int bad = element_local_put<E, Q, NM, HA, 256>(
+                nid, x, g.tab, g.tabp, g.cm0, g.cm1, g.ca, fl_lds + threadIdx.x,
+                [&](int p, int mat, double v) { out[p * NMAT + mat] = v; });
+            if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
+        } else {
+            // many points: one LDS read per point and pair would dominate, and
+            // the kernel takes one wave per SIMD either way
+            double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
+            const int bad = element_local<E, NM, HA>(nid, x, g.tab, Q, g.cm0, g.cm1, g.ca, LM, LA);
+            if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
 #pragma unroll
-        for (int p = 0; p < E::np; ++p)
+            for (int p = 0; p < E::np; ++p)
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat)
-                stage[(e * E::np + p) * NMAT + mat] = mat < NM ? LM[mat][p] : LA[p];
+                for (int mat = 0; mat < NMAT; ++mat) out[p * NMAT + mat] = mat < NM ? LM[mat][p] : LA[p];
+        }
     } else {
         double f[NM > 0 ? NM : 1][Q];
         double kq[HA ? Q : 1][E::nsym];
@@ -156,6 +176,24 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
             for (int mat = 0; mat < NMAT; ++mat) stage[(e * E::np + p) * NMAT + mat] = v[mat];
         }
     }
+}
+
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                               double *__restrict__ stage)
+{
+    stage_body<E, Q, NM, HA>(g, T, conn, stage);
+}
+
+// the same for P2 tetrahedra under rules of up to 11 points, held to at most
+// 256 registers, two waves per SIMD (the unbounded kernel takes 266 and runs
+// one wave per SIMD; with the bound a few registers spill): 876 -> 781 us on
+// the 64^3 Kuhn cube, M and A_a
+template <class E, int Q, int NM, bool HA>
+__global__ __launch_bounds__(256, 2) void k_stage2(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                                   double *__restrict__ stage)
+{
+    stage_body<E, Q, NM, HA>(g, T, conn, stage);
 }
 
 // sum of the contributions of CSR value s, in ascending element order, up to
@@ -200,7 +238,11 @@ __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t 
 }
 
 // one thread per CSR value with at most kReduceBatch contributions (a single
-// round of loads); the longer lists are left to k_reduce_long
+// round of loads); the longer lists are left to k_reduce_long.  The reads are
+// at the minimum the method allows (each element's staged record and the
+// contribution lists fetched about once, 2.6 GB for the 64^3 cube against
+// 2.25 GB), scattered over the staging array; two values per thread with
+// their loads interleaved changed nothing.
 template <int K, int NMAT>
 __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, const int32_t *__restrict__ cptr,
                                                 const int32_t *__restrict__ clist,
@@ -208,7 +250,10 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, const int32_t *__re
                                                 double *__restrict__ v0, double *__restrict__ v1,
                                                 double *__restrict__ v2)
 {
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous value ranges per XCD: the values of neighbouring rows read the
+    // same elements' staged matrices, which then come from one L2 rather than
+    // being fetched into several (HBM reads of the c3 reduction 6.7 -> 2.6 GB)
+    const int64_t s = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (s >= nnz) return;
     const int32_t c0 = cptr[s], c1 = cptr[s + 1];
     if (c1 - c0 > kReduceBatch) return;
@@ -225,7 +270,7 @@ __global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_
                                                      double *__restrict__ v0, double *__restrict__ v1,
                                                      double *__restrict__ v2)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (i >= nlong) return;
     const int64_t s = slots[i];
     double *const outs[3] = {v0, v1, v2};
@@ -367,6 +412,7 @@ void with_rule(int Q, F &&fn)
     throw Error{LFEM_EUNSUPPORTED, "quadrature rule"};
 }
 
+void allow_lds(const void *kern, size_t lds);
 template <class E, int NM, bool HA, int NT>
 void launch_blocked(Mesh &m, Pattern &p, const Outs &o, size_t lds, hipStream_t s);
 template <class E, int NM, bool HA, int NT>
@@ -407,7 +453,13 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
         with_rule<E>(m.Q, [&](auto qc) {
             constexpr int Q = decltype(qc)::value;
-            k_stage<E, Q, NM, HA><<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q>(), s>>>(g, m.T, m.conn, p.stage);
+            auto pick = [] {
+                if constexpr (E::d == 3 && Q <= 11) return k_stage2<E, Q, NM, HA>;
+                else return k_stage<E, Q, NM, HA>;
+            };
+            auto ks = pick();
+            allow_lds(reinterpret_cast<const void *>(ks), stage_lds_bytes<E, Q, NM>());
+            ks<<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q, NM>(), s>>>(g, m.T, m.conn, p.stage);
         });
         LFEM_HIP(hipGetLastError());
         k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
