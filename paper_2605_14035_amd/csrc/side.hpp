@@ -383,33 +383,42 @@ __device__ __forceinline__ void side_reduce(const BlockArgs &g, const SideBlock<
                               s.nloc, lds, rs);
 }
 
-// store the block's values and clear them in LDS
+// store the block's values and clear them in LDS.  Thread t stores the
+// values at global positions a0 + t + u NT, a0 = base rounded down to 16
+// values, so that every wave stores whole 128-byte lines (only the block's
+// first and last line are partial): the stores are non-temporal, and partial
+// lines written by two different store instructions reach memory as two
+// partial writes.
 template <int NMAT, int NT>
 __device__ __forceinline__ void side_write(const BlockArgs &g, int base, int nloc, double *lds, int rs)
 {
+    const int lead = base & 15;  // values of the first line that precede the block
 #pragma unroll
     for (int mat = 0; mat < NMAT; ++mat) {
         double *__restrict__ out = g.v[mat] + base;
-        double *reg = lds + mat * rs;
+        double *reg = lds + mat * rs;  // index i below is value i - lead of the block
         // eight LDS reads in flight per thread before their stores; the
         // values are written once and not read again here, so the stores are
         // non-temporal (they do not displace the coordinates and element
         // words that halo elements re-read from L2: about 8 % faster)
+        const int end = nloc + lead;
         int i = threadIdx.x;
-        for (; i + 7 * NT < nloc; i += 8 * NT) {
+        for (; i + 7 * NT < end; i += 8 * NT) {
             double t[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = reg[i + u * NT];
+            for (int u = 0; u < 8; ++u) t[u] = i + u * NT >= lead ? reg[i + u * NT - lead] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                __builtin_nontemporal_store(t[u], &out[i + u * NT]);
-                reg[i + u * NT] = 0.0;
+            for (int u = 0; u < 8; ++u)
+                if (i + u * NT >= lead) {
+                    __builtin_nontemporal_store(t[u], &out[i + u * NT - lead]);
+                    reg[i + u * NT - lead] = 0.0;
+                }
+        }
+        for (; i < end; i += NT)
+            if (i >= lead) {
+                __builtin_nontemporal_store(reg[i - lead], &out[i - lead]);
+                reg[i - lead] = 0.0;
             }
-        }
-        for (; i < nloc; i += NT) {
-            __builtin_nontemporal_store(reg[i], &out[i]);
-            reg[i] = 0.0;
-        }
     }
 }
 
