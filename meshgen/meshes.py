@@ -226,15 +226,74 @@ def p1_to_p2(V, F, edges):
 # --------------------------------------------------------------------------
 # P1 -> P3, P4 (segments and triangles)
 # --------------------------------------------------------------------------
+TET_FACES = ((0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3))
+
+
+def tet_lattice_alphas(p):
+    """Barycentric multi-indices (|alpha| = p) of the local nodes of an order-p
+    tetrahedron: vertices; per edge of TET_EDGES its p - 1 nodes from the
+    edge's first vertex; per face of TET_FACES its inner nodes (p = 3: (1,1,1);
+    p = 4: (2,1,1), (1,2,1), (1,1,2) on the face's vertices); the inner node
+    (1,1,1,1) for p = 4."""
+    out = []
+    for i in range(4):
+        a = [0] * 4
+        a[i] = p
+        out.append(a)
+    for u, v in TET_EDGES:
+        for i in range(1, p):
+            a = [0] * 4
+            a[u], a[v] = p - i, i
+            out.append(a)
+    for f in TET_FACES:
+        inner = [(1, 1, 1)] if p == 3 else [(2, 1, 1), (1, 2, 1), (1, 1, 2)] if p == 4 else []
+        for w in inner:
+            a = [0] * 4
+            for j, vert in enumerate(f):
+                a[vert] = w[j]
+            out.append(a)
+    if p == 4:
+        out.append([1, 1, 1, 1])
+    return out
+
+
+def _tet_to_pp(V, F, p):
+    """Order-p lattice nodes of straight tetrahedra.  A node is identified by
+    its barycentric position over global vertex ids, so nodes on shared edges
+    and faces are created once."""
+    alphas = tet_lattice_alphas(p)
+    ids = {}
+    coords = list(V)
+    conn = np.zeros((len(F), len(alphas)), dtype=np.int64)
+    for e, g in enumerate(F):
+        for a, al in enumerate(alphas):
+            key = tuple(sorted((int(g[j]), al[j]) for j in range(4) if al[j] > 0))
+            if len(key) == 1:
+                conn[e, a] = key[0][0]
+                continue
+            n = ids.get(key)
+            if n is None:
+                n = len(coords)
+                ids[key] = n
+                coords.append(sum(al[j] * V[g[j]] for j in range(4)) / p)
+            conn[e, a] = n
+    return np.array(coords), conn
+
+
 def p1_to_pp(V, F, p, edges):
-    """Lattice nodes of order p (3 or 4) on straight segments / triangles.
+    """Lattice nodes of order p (3 or 4) on straight segments / triangles /
+    tetrahedra.
 
     Local order: vertices; then for each local edge (u, v) of ``edges`` its
     p - 1 nodes from u to v (barycentric position (p - i, i) / p on the
     edge, i = 1..p-1); then interior triangle nodes, p = 3: (1,1,1)/3,
-    p = 4: (2,1,1)/4, (1,2,1)/4, (1,1,2)/4.  Nodes on an edge are created
-    once per distinct edge, from its lower to its higher vertex id, and each
-    element takes them in its own direction."""
+    p = 4: (2,1,1)/4, (1,2,1)/4, (1,1,2)/4; tetrahedra: edge nodes, then
+    the face and interior nodes of tet_lattice_alphas.  Nodes on an edge
+    are created once per distinct edge, from its lower to its higher vertex
+    id, and each element takes them in its own direction."""
+    if F.shape[1] == 4:
+        assert tuple(map(tuple, edges)) == TET_EDGES
+        return _tet_to_pp(np.asarray(V, dtype=np.float64), np.asarray(F), p)
     nV, T = len(V), len(F)
     keys = np.concatenate([_edge_keys(F[:, i], F[:, j], nV) for (i, j) in edges])
     uniq, inv = np.unique(keys, return_inverse=True)

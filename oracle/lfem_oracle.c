@@ -56,7 +56,7 @@ typedef double real;
 #define OR_ENOMEM 2
 #define OR_EDEGENERATE 3
 
-#define KMAX 15
+#define KMAX 35
 #define DMAX 3
 
 /* ---------------------------------------------------------------------- */
@@ -66,22 +66,29 @@ static const int SEG_E[1][2] = {{0, 1}};
 static const int TRI_E[3][2] = {{0, 1}, {1, 2}, {2, 0}};
 static const int TET_E[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
 
+static const int TET_F[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+
 int oracle_nodes_per_element(int d, int p)
 {
     if (p == 1) return d + 1;
     if (p == 2) return (d + 1) * (d + 2) / 2;
     if ((p == 3 || p == 4) && d == 1) return p + 1;
     if ((p == 3 || p == 4) && d == 2) return (p + 1) * (p + 2) / 2;
+    if ((p == 3 || p == 4) && d == 3) return (p + 1) * (p + 2) * (p + 3) / 6;
     return -1;
 }
 
-/* Orders 3 and 4 on segments and triangles (the paper notes that its assembly
- * extends to degree 3 and up, section 1; its mesh utility builds orders 2 to
- * 4, section 5.4).  Node a has the multi-index alpha (|alpha| = p)
+/* Orders 3 and 4 (the paper notes that its assembly extends to degree 3 and
+ * up, section 1; its mesh utility builds orders 2 to 4 in one to three
+ * dimensions, section 5.4).  Node a has the multi-index alpha (|alpha| = p)
  * of its barycentric position alpha / p, in the order: vertices; then for each
  * edge (u -> v) of the edge list its p - 1 nodes from u to v (alpha_u = p - i,
- * alpha_v = i, i = 1..p-1); then the interior nodes (p = 3: (1,1,1); p = 4:
- * (2,1,1), (1,2,1), (1,1,2)).  The Lagrange function of node alpha is
+ * alpha_v = i, i = 1..p-1); then the nodes inside the faces of a tetrahedron,
+ * face by face in the order (0,1,2), (0,1,3), (0,2,3), (1,2,3) (p = 3: its
+ * centroid (1,1,1); p = 4: (2,1,1), (1,2,1), (1,1,2) on the face's vertices
+ * in that order); then the interior nodes (triangle, p = 3: (1,1,1); p = 4:
+ * (2,1,1), (1,2,1), (1,1,2); tetrahedron, p = 4: (1,1,1,1)).  The Lagrange
+ * function of node alpha is
  *   phi_alpha = prod_j prod_{m < alpha_j} (p lambda_j - m) / (m + 1),
  * which is 1 at its node and 0 at every other node of the lattice. */
 static void node_alpha(int d, int p, int a, int *alpha)
@@ -94,8 +101,8 @@ static void node_alpha(int d, int p, int a, int *alpha)
     }
     a -= nv;
     {
-        int ne = (d == 1) ? 1 : 3;
-        const int(*E)[2] = (d == 1) ? SEG_E : TRI_E;
+        int ne = (d == 1) ? 1 : (d == 2 ? 3 : 6);
+        const int(*E)[2] = (d == 1) ? SEG_E : (d == 2 ? TRI_E : TET_E);
         if (a < ne * (p - 1)) {
             int e = a / (p - 1), i = a % (p - 1) + 1;
             alpha[E[e][0]] = p - i;
@@ -103,6 +110,18 @@ static void node_alpha(int d, int p, int a, int *alpha)
             return;
         }
         a -= ne * (p - 1);
+    }
+    if (d == 3) {
+        int nf = (p == 3) ? 1 : 3; /* nodes inside one face */
+        if (a < 4 * nf) {
+            const int *F = TET_F[a / nf];
+            alpha[F[0]] = alpha[F[1]] = alpha[F[2]] = 1;
+            if (p == 4) alpha[F[a % nf]] = 2;
+            return;
+        }
+        /* interior (p == 4) */
+        alpha[0] = alpha[1] = alpha[2] = alpha[3] = 1;
+        return;
     }
     /* interior (d == 2) */
     alpha[0] = alpha[1] = alpha[2] = 1;
@@ -148,7 +167,7 @@ static int basis_r(int d, int p, const real *xi, real *phi, real *dphi)
 {
     real lam[DMAX + 1], dlam[DMAX + 1][DMAX];
     int i, m;
-    if (d < 1 || d > 3 || p < 1 || p > 4 || (p > 2 && d > 2)) return OR_EINVAL;
+    if (d < 1 || d > 3 || p < 1 || p > 4) return OR_EINVAL;
     lam[0] = 1.0;
     for (m = 0; m < d; m++) {
         lam[0] -= xi[m];
@@ -307,7 +326,6 @@ static int make_type(etype *t, int surface, int d, int p, int Q, const double *q
                      const double *qw)
 {
     if (d < 1 || d > 3 || p < 1 || p > 4 || Q < 1) return OR_EINVAL;
-    if (p > 2 && d > 2) return OR_EINVAL;
     if (surface && d == 3) return OR_EINVAL;
     if (!surface && d == 1) return OR_EINVAL;
     t->surface = surface;

@@ -1,6 +1,7 @@
-"""Pins of the oracle's cubic and quartic elements on segments and triangles
-(degree 3 and up, which the paper notes its assembly extends to, section 1;
-its mesh utility builds orders 2 to 4, section 5.4).
+"""Pins of the oracle's cubic and quartic elements on segments, triangles and
+tetrahedra (degree 3 and up, which the paper notes its assembly extends to,
+section 1; its mesh utility builds orders 2 to 4 in one to three dimensions,
+section 5.4).
 
 * the nodal basis against an independent construction: the Lagrange basis of
   the node lattice obtained by solving the Vandermonde system of the
@@ -8,10 +9,13 @@ its mesh utility builds orders 2 to 4, section 5.4).
   formula the oracle uses); values and gradients at random points;
 * the delta property at the nodes, partition of unity;
 * single affine elements of every type: mass and stiffness matrices against
-  exact rational integration of that basis (rules of degree >= 2p);
+  exact rational integration of that basis (rules of degree >= 2p; for the
+  quartic tetrahedron under the degree-7 rule the stiffness (degree 6) and
+  the mass row sums (degree 4) are exact, the full mass (degree 8) is not);
 * meshes from the P1 -> Pp converter: node positions are the lattice points of
-  each element, 1^T M 1 is the area (flat) and A 1 = 0, sum_k x_k^T A x_k =
-  d 1^T M 1 (linear reproduction) on a curved sphere.
+  each element, 1^T M 1 is the area or volume (flat) and A 1 = 0,
+  sum_k x_k^T A x_k = d 1^T M 1 (linear reproduction) on a curved sphere and
+  on a tetrahedral cube with curved (jittered) nodes.
 """
 
 import itertools
@@ -24,7 +28,8 @@ import oracle
 from meshgen import meshes as mg
 from test_oracle_closed_forms import AFFINE_CASES, padd, pgrad_ref, pint, pmul
 
-EDGES = {1: [(0, 1)], 2: [(0, 1), (1, 2), (2, 0)]}
+EDGES = {1: [(0, 1)], 2: [(0, 1), (1, 2), (2, 0)], 3: [(0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3)]}
+FACES = [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]
 
 
 def node_alphas(d, p):
@@ -45,6 +50,16 @@ def node_alphas(d, p):
             out.append([1, 1, 1])
         elif p == 4:
             out += [[2, 1, 1], [1, 2, 1], [1, 1, 2]]
+    if d == 3:
+        inner = [(1, 1, 1)] if p == 3 else [(2, 1, 1), (1, 2, 1), (1, 1, 2)] if p == 4 else []
+        for f in FACES:
+            for w in inner:
+                a = [0] * 4
+                for j, v in enumerate(f):
+                    a[v] = w[j]
+                out.append(a)
+        if p == 4:
+            out.append([1, 1, 1, 1])
     return out
 
 
@@ -84,7 +99,7 @@ def peval(poly, lam):
     return sum(float(c) * np.prod([lam[j] ** e for j, e in enumerate(mon)]) for mon, c in poly.items())
 
 
-CASES = [(d, p) for d in (1, 2) for p in (3, 4)]
+CASES = [(d, p) for d in (1, 2, 3) for p in (3, 4)]
 
 
 @pytest.mark.parametrize("d,p", CASES)
@@ -117,11 +132,11 @@ def test_delta_property_and_partition_of_unity(d, p):
 
 
 def high_rule(d):
-    return 6 if d == 1 else 16
+    return {1: 6, 2: 16, 3: 35}[d]
 
 
 @pytest.mark.parametrize("p", [3, 4])
-@pytest.mark.parametrize("domain,dim,verts", [c for c in AFFINE_CASES if c[1] <= 2])
+@pytest.mark.parametrize("domain,dim,verts", AFFINE_CASES)
 def test_affine_exact_rational(domain, dim, verts, p):
     import sympy
     X = [[Fraction(c) for c in v] for v in verts]
@@ -134,14 +149,15 @@ def test_affine_exact_rational(domain, dim, verts, p):
     k = len(phis)
     grads = [[pgrad_ref(ph, dim, m) for m in range(dim)] for ph in phis]
     Mex, Aex = np.zeros((k, k)), np.zeros((k, k))
+    Gq = [[Fraction(int(Gi[i, j].p), int(Gi[i, j].q)) for j in range(dim)] for i in range(dim)]
     for a in range(k):
-        for b in range(k):
-            Mex[a, b] = float(pint(pmul(phis[a], phis[b]), dim))
+        for b in range(a, k):
+            Mex[a, b] = Mex[b, a] = float(pint(pmul(phis[a], phis[b]), dim))
             s = Fraction(0)
             for i in range(dim):
                 for j in range(dim):
-                    s += Fraction(int(Gi[i, j].p), int(Gi[i, j].q)) * pint(pmul(grads[a][i], grads[b][j]), dim)
-            Aex[a, b] = float(s)
+                    s += Gq[i][j] * pint(pmul(grads[a][i], grads[b][j]), dim)
+            Aex[a, b] = Aex[b, a] = float(s)
     Mex *= mu
     Aex *= mu
     # one element whose nodes are the lattice points of the rational vertices
@@ -152,8 +168,23 @@ def test_affine_exact_rational(domain, dim, verts, p):
     m = dict(domain=domain, dim=dim, order=p, quad=high_rule(dim), coords=coords, conn=conn)
     M = oracle.element_matrices(m, "mass")[0]
     A = oracle.element_matrices(m, "stiffness")[0]
-    assert np.abs(M - Mex).max() <= 1e-13 * np.abs(Mex).max()
     assert np.abs(A - Aex).max() <= 1e-12 * np.abs(Aex).max()
+    if dim == 3 and p == 4:
+        # the degree-7 rule integrates the row sums (int phi_a, degree 4) exactly,
+        # not the degree-8 products; those equal the rule's own sum
+        # mu sum_q w_q phi_a phi_b (xi_q), with phi from the rational construction
+        assert np.abs(M.sum(1) - Mex.sum(1)).max() <= 1e-13 * np.abs(Mex.sum(1)).max()
+        from oracle import quadrature
+        qp, qw = quadrature.rule(3, 35)
+        Mq = np.zeros((k, k))
+        for xq, wq in zip(qp, qw):
+            lamq = np.concatenate([[1 - xq.sum()], xq])
+            ph = np.array([peval(f, lamq) for f in phis])
+            Mq += wq * np.outer(ph, ph)
+        Mq *= mu
+        assert np.abs(M - Mq).max() <= 1e-13 * np.abs(Mq).max()
+    else:
+        assert np.abs(M - Mex).max() <= 1e-13 * np.abs(Mex).max()
 
 
 @pytest.mark.parametrize("p", [3, 4])
@@ -200,3 +231,44 @@ def test_sphere_linear_reproduction(p):
     lhs = sum(coords[c] @ (A @ coords[c]) for c in range(3))
     assert abs(lhs - 2 * M.sum()) <= 1e-12 * M.sum()
     assert abs(M.sum() - 4 * np.pi) <= 2e-3 * 4 * np.pi  # curved order-p sphere area
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_converter_places_tetrahedral_lattice_nodes(p):
+    V, F, _ = mg.kuhn_cube(2, order=1)
+    W, G = mg.p1_to_pp(V, F, p, mg.TET_EDGES)
+    assert G.shape[1] == len(node_alphas(3, p))
+    for e in range(len(F)):
+        X = V[F[e]]
+        for a, al in enumerate(node_alphas(3, p)):
+            want = sum(al[j] / p * X[j] for j in range(4))
+            assert np.abs(W[G[e, a]] - want).max() <= 1e-15
+    # one node per lattice point: the (2 p + 1)^3 points of the two-cell cube
+    assert len(W) == (2 * p + 1) ** 3
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_tetrahedral_volume_kernel_and_linear_reproduction(p):
+    """Straight Kuhn cube: 1^T M 1 = 1 and A 1 = 0; with the edge, face and
+    inner nodes moved off the lattice (curved elements), linear reproduction
+    sum_k x_k^T A x_k = 3 * 1^T M 1 still holds."""
+    V, F, _ = mg.kuhn_cube(2, order=1)
+    W, G = mg.p1_to_pp(V, F, p, mg.TET_EDGES)
+    coords, conn = mg.to_soa(W, G)
+    m = dict(domain="bulk", dim=3, order=p, quad=35, coords=coords, conn=conn)
+    N = coords.shape[1]
+    M = oracle.to_scipy(N, oracle.assemble(m, "mass"))
+    A = oracle.to_scipy(N, oracle.assemble(m, "stiffness"))
+    assert abs(M.sum() - 1.0) <= 1e-13
+    assert np.abs(A @ np.ones(N)).max() <= 1e-12
+    rng = np.random.default_rng(30 + p)
+    Wc = W.copy()
+    inner = np.all((W > 1e-12) & (W < 1 - 1e-12), axis=1) & (np.arange(len(W)) >= len(V))
+    Wc[inner] += rng.uniform(-0.01, 0.01, size=(int(inner.sum()), 3))
+    cc, _ = mg.to_soa(Wc, G)
+    mc = dict(m, coords=cc)
+    Mc = oracle.to_scipy(N, oracle.assemble(mc, "mass"))
+    Ac = oracle.to_scipy(N, oracle.assemble(mc, "stiffness"))
+    lhs = sum(cc[c] @ (Ac @ cc[c]) for c in range(3))
+    assert abs(lhs - 3 * Mc.sum()) <= 1e-12 * Mc.sum()
+    assert abs(Mc.sum() - 1.0) <= 1e-3  # boundary nodes fixed: the volume moves only slightly
