@@ -376,6 +376,27 @@ def tets_rows(lf, torch, meshgen, atomic=False):
     rows["tets_c3_degree7"].update({"flops_per_element": flops7, "tflops": flops7 * T3 / t7 / 1e12,
                                     "frac_fp64_peak": flops7 * T3 / t7 / 78.6e12})
     dm7.close()
+    # orders 3 and 4 on tetrahedra (one wave per element, staged reduction): M + A on Kuhn cubes of
+    # about 250k nodes, 35-point rule
+    from meshgen import meshes as mg
+    for p_ord, n_c in ((3, 20), (4, 16)):
+        V, F, _ = mg.kuhn_cube(n_c, order=1)
+        V, F = mg.p1_to_pp(V, F, p_ord, mg.TET_EDGES)
+        V, F, _ = mg.sfc_reorder(V, F)
+        cp, kp = mg.to_soa(V, F)
+        dmp = lf.DeviceMesh.from_dict(dict(domain="bulk", dim=3, order=p_ord, quad=35, coords=cp, conn=kp))
+        dmp.build_pattern()
+        op = {k: torch.empty(dmp.nnz, dtype=torch.float64, device="cuda") for k in ("M", "A")}
+        Np, Tp, nnzp = dmp.N, dmp.T, dmp.nnz
+        ms = event_times(torch, lambda: lf.lfem_assemble(dmp.handle, dmp.pattern, lf.LFEM_M | lf.LFEM_A, None,
+                                                         None, op["M"], op["A"], None, lf.LFEM_SCATTER_AUTO),
+                         reps=5, warm=1)
+        rows[f"tets_order{p_ord}"] = row_entry(
+            f"M + A on order-{p_ord} tetrahedra, Kuhn cube {n_c}^3 x 6 ({Tp} elements, {Np} nodes), 35-point rule",
+            ms, Tp, 3 * Np * 8 + kp.shape[0] * Tp * 4 + 2 * nnzp * 8, nodes=Np, nnz=nnzp,
+            nodes_per_s=Np / (ms[1] * 1e-3), scatter="staged")
+        del op
+        dmp.close()
     if atomic:
         dma = lf.DeviceMesh.from_dict(m3)
         dma.build_pattern()

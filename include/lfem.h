@@ -5,9 +5,10 @@
  * What it computes.  For a mesh of linear (P1) or quadratic (P2)
  * isoparametric simplices -- curves in R^2, surfaces in R^3, bulk domains in
  * R^2 and R^3 (the element types of the paper's table of supported elements,
- * section 5) -- and of orders 3 and 4 on segments and triangles (the paper
- * notes its assembly extends to degree 3 and up, section 1, and its mesh
- * utility builds orders 2 to 4, section 5.4) -- it assembles in FP64:
+ * section 5) -- and of orders 3 and 4 on segments, triangles and tetrahedra
+ * (the paper notes its assembly extends to degree 3 and up, section 1, and
+ * its mesh utility builds orders 2 to 4 in one to three dimensions, section
+ * 5.4) -- it assembles in FP64:
  *
  *   mass              M_ij   = sum_E sum_q w_q mu_E(xi_q) phi_i phi_j
  *   stiffness         A_ij   = sum_E sum_q w_q mu_E(xi_q) grad phi_i . grad phi_j
@@ -32,8 +33,12 @@
  *    in anticlockwise order, then edge nodes: segment (0,1); triangle
  *    (0,1), (1,2), (2,0); tetrahedron (0,1), (1,2), (0,2), (0,3), (1,3), (2,3).
  *    Orders 3 and 4: the p - 1 nodes of each edge from its first corner to
- *    its second, then the interior nodes (order 3: the centroid; order 4:
- *    (2,1,1)/4, (1,2,1)/4, (1,1,2)/4 in barycentric coordinates).
+ *    its second; on tetrahedra then the nodes inside the faces (0,1,2),
+ *    (0,1,3), (0,2,3), (1,2,3), face by face (order 3: the face centroid;
+ *    order 4: (2,1,1)/4, (1,2,1)/4, (1,1,2)/4 over the face's corners in
+ *    that order); then the interior nodes (triangle, order 3: the centroid,
+ *    order 4: (2,1,1)/4, (1,2,1)/4, (1,1,2)/4; tetrahedron, order 4: the
+ *    centroid) in barycentric coordinates.
  *  - Every array argument is a DEVICE pointer owned by the caller; the
  *    library never frees it.  A mesh keeps the coords / conn pointers it was
  *    given (no copy): they must stay valid, and conn unchanged, for the
@@ -86,8 +91,10 @@ typedef struct lfem_batch_s *lfem_batch_t;
 
 /*
  * Create a mesh handle.  domain: LFEM_SURFACE or LFEM_BULK; dim: manifold
- * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1 or 2, or 3 or 4 for
- * d <= 2 (these take the high-order rules and the staged scatter).  The ambient
+ * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1, 2, 3 or 4 (orders 3
+ * and 4 take the high-order rules and the staged scatter; on tetrahedra the
+ * load vector, the mean-curvature-flow terms, the shape gradient and the
+ * energy are built for orders 1 and 2 only: LFEM_EUNSUPPORTED).  The ambient
  * dimension is n_amb = d + 1 (surface) or d (bulk), so coords has
  * n_amb * n_nodes entries and conn has k * n_elems entries, k = C(order+d, d).
  * quad_points selects the quadrature rule on the reference simplex by its
@@ -103,12 +110,13 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * more on segments, Dunavant of degree 8 on triangles, degree 7 on
  * tetrahedra), with the weights summing to the reference measure.  Batched assembly takes the two default rules only.
  * Orders 3 and 4 take only the high-order rules (defaults: segment 5 points
- * for order 3 and 6 for order 4; triangle 16).
+ * for order 3 and 6 for order 4; triangle 16; tetrahedron 35).
  * Uploads the reference tables and builds the node -> element incidence
  * asynchronously on stream (device buffers are allocated with hipMalloc
  * first); use the handle on the same stream, or synchronise it before using
  * the handle on another.
- * Errors: LFEM_EINVAL (sizes, nulls, n_elems * k >= 2^31),
+ * Errors: LFEM_EINVAL (sizes, nulls), LFEM_ERANGE (n_elems >= 2^25 or
+ * n_elems * k >= 2^31),
  * LFEM_EUNSUPPORTED (type/rule), LFEM_ENOMEM, LFEM_EHIP.
  */
 lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
@@ -124,12 +132,14 @@ lfem_status lfem_mesh_set_coords(lfem_mesh_t m, const double *coords);
 /*
  * Symbolic phase (once per topology): build the CSR pattern, the
  * element -> CSR slot map (one byte per local pair: the column offset inside
- * the row) and the row-block schedule of the blocked scatter.  The pattern is
+ * the row; two bytes for elements of more than 15 nodes, the cubic and
+ * quartic tetrahedra) and the row-block schedule of the blocked scatter.  The pattern is
  * the structural sparsity of the element array (the paper's sparse() step
  * without its value-dependent dropping).  SYNCHRONISES stream once to learn
  * nnz and to build the block schedule on the host.
  * Errors: LFEM_EINVAL (a conn entry outside [0, N) or repeated inside an
- * element), LFEM_ERANGE (nnz >= 2^31, or a row with more than 255 entries),
+ * element), LFEM_ERANGE (nnz >= 2^31, or a row with more than 255 entries,
+ * 1023 for elements of more than 15 nodes),
  * LFEM_ENOMEM, LFEM_EHIP.
  */
 lfem_status lfem_pattern_build(lfem_mesh_t m, void *stream, lfem_pattern_t *out);
@@ -161,10 +171,11 @@ lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
  * weighted mass (required with LFEM_MC).  vals_m / vals_a / vals_mc: outputs
  * of nnz doubles each, overwritten (required for the selected matrices).
  * scatter: LFEM_SCATTER_*.  The blocked and staged scatters are bitwise
- * reproducible run to run; the atomic one is not.  The first staged call on
- * a pattern builds its contribution lists and SYNCHRONISES stream once;
- * later calls are asynchronous and allocate nothing while the staging
- * buffer suffices.
+ * reproducible run to run; the atomic one is not.  Orders 3 and 4 have no
+ * block schedule: a blocked request takes the staged scatter.  The first
+ * staged call on a pattern builds its contribution lists and SYNCHRONISES
+ * stream once (LFEM_EUNSUPPORTED if k^2 * n_elems >= 2^31); later calls are
+ * asynchronous and allocate nothing while the staging buffer suffices.
  * Degenerate elements (measure not positive and finite) still produce values
  * and increment the mesh's counter (lfem_status_get).
  */

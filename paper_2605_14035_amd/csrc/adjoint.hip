@@ -315,8 +315,8 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T,
 #pragma unroll
         for (int i = 0; i < U; ++i)
             if (i < cnt) {
-                const int64_t e = inc[i] >> 4;
-                const int a = inc[i] & 15;
+                const int64_t e = inc[i] >> kIncShift;
+                const int a = inc[i] & kIncMask;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) v[i][c] = stage[(a * T + e) * NCH + c];
             }

@@ -79,6 +79,7 @@ void release_pattern(Pattern &p)
     dev_free(p.row_ptr);
     dev_free(p.col_idx);
     dev_free(p.off8);
+    dev_free(p.off16);
     dev_free(p.cptr);
     dev_free(p.clist);
     dev_free(p.long_slots);
@@ -118,21 +119,21 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
         LFEM_REQUIRE(out, LFEM_EINVAL, "out is null");
         *out = nullptr;
         const int et = etype_of(domain, dim, order);
-        LFEM_REQUIRE(order >= 1 && order <= 4 && (order <= 2 || dim <= 2), LFEM_EUNSUPPORTED,
-                     "order must be 1 or 2 (3 and 4 on segments and triangles)");
+        LFEM_REQUIRE(order >= 1 && order <= 4, LFEM_EUNSUPPORTED, "order must be 1, 2, 3 or 4");
         LFEM_REQUIRE(et >= 0, LFEM_EUNSUPPORTED, "unsupported (domain, dim)");
         LFEM_REQUIRE(n_nodes >= 0 && n_elems >= 0, LFEM_EINVAL, "negative size");
         LFEM_REQUIRE(n_nodes < (int64_t(1) << 31) - 1, LFEM_ERANGE, "n_nodes >= 2^31 - 1");
         const int k = nodes_per_elem(dim, order);
-        LFEM_REQUIRE(n_elems < (int64_t(1) << 27) && n_elems * k < (int64_t(1) << 31), LFEM_ERANGE,
-                     "too many elements for int32 incidence indices");
+        LFEM_REQUIRE(n_elems < (int64_t(1) << (31 - kIncShift)) && n_elems * k < (int64_t(1) << 31), LFEM_ERANGE,
+                     "too many elements for int32 incidence codes (at most 2^25)");
         LFEM_REQUIRE(n_nodes == 0 || coords, LFEM_EINVAL, "coords is null");
         LFEM_REQUIRE(n_elems == 0 || conn, LFEM_EINVAL, "conn is null");
         RefTable tab;
         LFEM_REQUIRE(build_ref_table(dim, order, quad_points, tab), LFEM_EUNSUPPORTED,
                      "no quadrature rule with that number of points for this simplex");
-        LFEM_REQUIRE(order <= 2 || tab.Q >= (dim == 1 ? 5 : 16), LFEM_EUNSUPPORTED,
-                     "orders 3 and 4 take the high-order rules (segment 5 or 6, triangle 16 points)");
+        LFEM_REQUIRE(order <= 2 || tab.Q >= (dim == 1 ? 5 : (dim == 2 ? 16 : 35)), LFEM_EUNSUPPORTED,
+                     "orders 3 and 4 take the high-order rules (segment 5 or 6, triangle 16, "
+                     "tetrahedron 35 points)");
         auto *m = new lfem_mesh_s();
         try {
             m->domain = domain;
@@ -410,8 +411,8 @@ lfem_status lfem_reference_table(int dim, int order, int quad_points, int *q_out
 {
     return guarded([&] {
         LFEM_REQUIRE(q_out && k_out, LFEM_EINVAL, "null q_out or k_out");
-        LFEM_REQUIRE(dim >= 1 && dim <= 3 && order >= 1 && order <= 4 && (order <= 2 || dim <= 2),
-                     LFEM_EUNSUPPORTED, "no element of that dimension and order");
+        LFEM_REQUIRE(dim >= 1 && dim <= 3 && order >= 1 && order <= 4, LFEM_EUNSUPPORTED,
+                     "no element of that dimension and order");
         RefTable tab;
         LFEM_REQUIRE(build_ref_table(dim, order, quad_points, tab), LFEM_EUNSUPPORTED,
                      "no quadrature rule with that number of points for this simplex");

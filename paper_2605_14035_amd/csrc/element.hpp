@@ -50,12 +50,12 @@ struct ET {
     static constexpr int d = D;
     static constexpr int p = P;
     static constexpr int n = SURF ? D + 1 : D;
-    static constexpr int k = D == 1 ? P + 1 : (D == 2 ? (P + 1) * (P + 2) / 2 : (P == 1 ? 4 : 10));
+    static constexpr int k = D == 1 ? P + 1 : (D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6);
     static constexpr int np = k * (k + 1) / 2;
     static constexpr int nh = P == 2 ? D * (D + 1) / 2 : 0;  // distinct Hessian slots (l <= m)
     // orders 1 and 2: J(xi) = J0 + sum_l xi_l H_l with compile-time basis
-    // coefficients; orders 3 and 4 (segments, triangles): J(xi) from the
-    // tabulated reference gradients at the point
+    // coefficients; orders 3 and 4: J(xi) from the tabulated reference
+    // gradients at the point
     static constexpr bool affine_j = P <= 2;
     // per-quadrature-point table: [w, xi (d), phi (k), grad phi (k*d), phi_a phi_b (np)]
     static constexpr int off_xi = 1;

@@ -43,15 +43,16 @@ inline void dev_free(void *p)
 // ---------------------------------------------------------------------------
 // element types: (surface?, manifold dimension d, order p)
 // ---------------------------------------------------------------------------
-// orders 3 and 4 (segments and triangles) follow the eight original types
+// orders 3 and 4 (segments, triangles, then tetrahedra) follow the eight
+// original types
 enum EType : int {
     S1P1 = 0, S1P2, S2P1, S2P2, B2P1, B2P2, B3P1, B3P2,
-    S1P3, S1P4, S2P3, S2P4, B2P3, B2P4, NUM_ETYPES
+    S1P3, S1P4, S2P3, S2P4, B2P3, B2P4, B3P3, B3P4, NUM_ETYPES
 };
 
 inline int etype_of(int domain, int d, int p)
 {
-    if (p < 1 || p > 4 || (p > 2 && d > 2)) return -1;
+    if (p < 1 || p > 4) return -1;
     if (p <= 2) {
         if (domain == LFEM_SURFACE && d == 1) return p == 1 ? S1P1 : S1P2;
         if (domain == LFEM_SURFACE && d == 2) return p == 1 ? S2P1 : S2P2;
@@ -62,22 +63,29 @@ inline int etype_of(int domain, int d, int p)
     if (domain == LFEM_SURFACE && d == 1) return p == 3 ? S1P3 : S1P4;
     if (domain == LFEM_SURFACE && d == 2) return p == 3 ? S2P3 : S2P4;
     if (domain == LFEM_BULK && d == 2) return p == 3 ? B2P3 : B2P4;
+    if (domain == LFEM_BULK && d == 3) return p == 3 ? B3P3 : B3P4;
     return -1;
 }
 
-// largest element (quartic triangle) and the 32-bit words of its k x k
-// byte slot map
-constexpr int kMaxNodes = 15;
+// largest element (quartic tetrahedron); elements of up to kMaxNodes8 nodes
+// keep a byte slot map (rows of at most 255 entries), larger ones a 16-bit
+// map (rows of at most kMaxRowWide entries)
+constexpr int kMaxNodes = 35;
+constexpr int kMaxNodes8 = 15;
+constexpr int kMaxRowWide = 1023;
+// incidences are coded e << kIncShift | a (local node a < 2^kIncShift)
+constexpr int kIncShift = 6;
+constexpr int kIncMask = (1 << kIncShift) - 1;
 // contributions of one CSR value loaded at once by the staged reduction; the
 // values with longer lists (diagonals of well-connected nodes) are summed by
 // a second, small launch so that the main one needs a single round of loads
 constexpr int kReduceBatch = 8;
-constexpr int kMaxSlotWords = (kMaxNodes * kMaxNodes + 3) / 4;
+constexpr int kMaxSlotWords = (kMaxNodes8 * kMaxNodes8 + 3) / 4;
 
 // nodes of the order-p Lagrange element: (p + d choose d)
 inline int nodes_per_elem(int d, int p)
 {
-    return d == 1 ? p + 1 : (d == 2 ? (p + 1) * (p + 2) / 2 : (p == 1 ? 4 : 10));
+    return d == 1 ? p + 1 : (d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6);
 }
 
 // Reference data per quadrature point q, `stride` doubles each:
@@ -116,7 +124,7 @@ struct Mesh {
     double *tabp = nullptr;          // device pair-major reference tensors
     RefTable host_tab;
     int32_t *ne_ptr = nullptr;       // [N+1] node -> incidence offsets
-    int32_t *ne = nullptr;           // [k*T] incidences e*16 + a, ascending per node
+    int32_t *ne = nullptr;           // [k*T] incidences e << kIncShift | a, ascending per node
     int32_t *flags = nullptr;        // [4] device flags: [0] bad index, [1] repeated node
     unsigned long long *degenerate = nullptr;
     double *scratch = nullptr;       // adjoint staging, grown on demand
@@ -163,12 +171,13 @@ struct Pattern {
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;
     int32_t *col_idx = nullptr;
-    uint8_t *off8 = nullptr;   // [T][kkp] column offset of (a,b) in row conn[a]
+    uint8_t *off8 = nullptr;   // [T][kkp] column offset of (a,b) in row conn[a] (k <= kMaxNodes8)
+    uint16_t *off16 = nullptr; // [T][k*k] the same, 16 bits (k > kMaxNodes8)
     int kkp = 0;               // bytes per element (k*k rounded up to 4)
     int max_row = 0;
     // staged scatter (built on first use)
     int32_t *cptr = nullptr;   // [nnz+1]
-    int32_t *clist = nullptr;  // [k*k*T] contributions e*256 + a*k + b, ascending per slot
+    int32_t *clist = nullptr;  // [k*k*T] contributions e*k*k + a*k + b, ascending per slot
     int32_t *long_slots = nullptr;  // [nlong] slots with more than kReduceBatch contributions, ascending
     int64_t nlong = 0;
     double *stage = nullptr;

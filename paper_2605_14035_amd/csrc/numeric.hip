@@ -58,7 +58,9 @@ void launch_numeric(Mesh &m, Pattern &p, const NumericOut &no, int variant, hipS
     case B2P3:
     case B2P4: numeric_planar(m, p, no, variant, s); break;
     case B3P1:
-    case B3P2: numeric_tet(m, p, no, variant, s); break;
+    case B3P2:
+    case B3P3:
+    case B3P4: numeric_tet(m, p, no, variant, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
     }
 }

@@ -26,6 +26,7 @@
 //             share no node).
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 
 #include <map>
@@ -196,6 +197,133 @@ __global__ __launch_bounds__(256, 2) void k_stage2(const BlockArgs g, int64_t T,
     stage_body<E, Q, NM, HA>(g, T, conn, stage);
 }
 
+// Orders 3 and 4 on tetrahedra: 20 and 35 nodes, 210 and 630 local pairs,
+// more than one thread's registers hold.  One wave per element: lanes
+// q < Q evaluate the geometry of point q (Jacobian from the tabulated
+// reference gradients, measure, inverse metric) into LDS, then each lane
+// takes the pairs p = lane, lane + 64, ... and forms their values
+//   M_ab = sum_q f_q phi_a phi_b,  A_ab = sum_q g_a^T K'_q g_b,
+// f_q = w_q mu_q c_h(xi_q), K'_q = w_q mu_q a_h(xi_q) K_q, from the point data
+// and the reference values (also in LDS).  The values are staged element by
+// element for the staged reduction, or with ATOMIC added to the CSR values.
+template <class E, int Q, int NM, bool HA, bool ATOMIC>
+__global__ __launch_bounds__(64) void k_wave(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                             double *__restrict__ stage, const int32_t *__restrict__ row_ptr,
+                                             const uint16_t *__restrict__ off16)
+{
+    constexpr int K = E::k, D = E::d, NA = E::n, NP = E::np, NMAT = NM + (HA ? 1 : 0);
+    constexpr int RS = 1 + K + K * D;            // per point: weight, phi (K), grad phi (K x D)
+    constexpr int NMS = NM > 0 ? NM : 1;
+    constexpr int QS = NMS + 6;                  // per point: mass factors, then w mu a_h K (m <= l)
+    static_assert(D == 3 && Q <= 64, "one lane per point of a tetrahedral rule");
+    __shared__ double ref[Q * RS];
+    __shared__ double xs[K * NA];
+    __shared__ double qd[Q * QS];
+    __shared__ int32_t nid[K];
+    __shared__ uint8_t pa[NP], pb[NP];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < Q * RS; i += 64) {
+        const int q = i / RS, j = i - q * RS;
+        const int src = j == 0 ? 0 : (j <= K ? E::off_phi + (j - 1) : E::off_g + (j - 1 - K));
+        ref[i] = g.tab[q * E::stride + src];
+    }
+    for (int p = lane; p < NP; p += 64) {  // pair p = (a, b), a <= b, row-major upper triangle
+        int a = 0, first = 0;
+        while (first + (K - a) <= p) {
+            first += K - a;
+            ++a;
+        }
+        pa[p] = static_cast<uint8_t>(a);
+        pb[p] = static_cast<uint8_t>(a + (p - first));
+    }
+    const double *cms[2] = {g.cm0, g.cm1};
+    for (int64_t e = blockIdx.x; e < T; e += gridDim.x) {
+        __syncthreads();  // the previous element's LDS data are consumed
+        if (lane < K) nid[lane] = conn[lane * T + e];
+        __syncthreads();
+        for (int i = lane; i < K * NA; i += 64) {
+            const int a = i / NA, c = i - a * NA;
+            xs[i] = g.coords[c * g.N + nid[a]];
+        }
+        __syncthreads();
+        if (lane < Q) {
+            const double *r = ref + lane * RS;
+            double J[NA][D];
+#pragma unroll
+            for (int c = 0; c < NA; ++c)
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    double acc = 0.0;
+                    for (int a = 0; a < K; ++a) acc = fma(xs[a * NA + c], r[1 + K + a * D + m], acc);
+                    J[c][m] = acc;
+                }
+            double Km[D][D], mu;
+            geometry<E>(J, Km, mu);
+            if (!(mu > 0.0 && mu < INFINITY)) atomicAdd(g.degenerate, 1ull);
+            const double wmu = r[0] * mu;
+            double *qq = qd + lane * QS;
+#pragma unroll
+            for (int s = 0; s < NM; ++s) {
+                double f = wmu;
+                if (cms[s]) {
+                    double ch = 0.0;
+                    for (int a = 0; a < K; ++a) ch = fma(cms[s][nid[a]], r[1 + a], ch);
+                    f *= ch;
+                }
+                qq[s] = f;
+            }
+            if constexpr (HA) {
+                double fa = wmu;
+                if (g.ca) {
+                    double ah = 0.0;
+                    for (int a = 0; a < K; ++a) ah = fma(g.ca[nid[a]], r[1 + a], ah);
+                    fa *= ah;
+                }
+                qq[NMS + 0] = fa * Km[0][0];
+                qq[NMS + 1] = fa * Km[0][1];
+                qq[NMS + 2] = fa * Km[0][2];
+                qq[NMS + 3] = fa * Km[1][1];
+                qq[NMS + 4] = fa * Km[1][2];
+                qq[NMS + 5] = fa * Km[2][2];
+            }
+        }
+        __syncthreads();
+        for (int p = lane; p < NP; p += 64) {
+            const int a = pa[p], b = pb[p];
+            double v[NMAT];
+#pragma unroll
+            for (int mat = 0; mat < NMAT; ++mat) v[mat] = 0.0;
+            for (int q = 0; q < Q; ++q) {
+                const double *r = ref + q * RS;
+                const double *qq = qd + q * QS;
+                const double pp = r[1 + a] * r[1 + b];
+#pragma unroll
+                for (int s = 0; s < NM; ++s) v[s] = fma(qq[s], pp, v[s]);
+                if constexpr (HA) {
+                    const double *ga = r + 1 + K + a * D, *gb = r + 1 + K + b * D;
+                    const double h0 = fma(qq[NMS + 0], ga[0], fma(qq[NMS + 1], ga[1], qq[NMS + 2] * ga[2]));
+                    const double h1 = fma(qq[NMS + 1], ga[0], fma(qq[NMS + 3], ga[1], qq[NMS + 4] * ga[2]));
+                    const double h2 = fma(qq[NMS + 2], ga[0], fma(qq[NMS + 4], ga[1], qq[NMS + 5] * ga[2]));
+                    v[NM] = fma(h0, gb[0], fma(h1, gb[1], fma(h2, gb[2], v[NM])));
+                }
+            }
+            if constexpr (ATOMIC) {
+                const int32_t sab = row_ptr[nid[a]] + off16[(e * K + a) * K + b];
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sab, v[mat]);
+                if (a != b) {
+                    const int32_t sba = row_ptr[nid[b]] + off16[(e * K + b) * K + a];
+#pragma unroll
+                    for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sba, v[mat]);
+                }
+            } else {
+#pragma unroll
+                for (int mat = 0; mat < NMAT; ++mat) stage[(e * NP + p) * NMAT + mat] = v[mat];
+            }
+        }
+    }
+}
+
 // sum of the contributions of CSR value s, in ascending element order, up to
 // kReduceBatch loads in flight
 template <int K, int NMAT>
@@ -217,8 +345,8 @@ __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t 
 #pragma unroll
         for (int i = 0; i < U; ++i)
             if (i < cnt) {
-                const int64_t e = code[i] >> 8;
-                const int ab = code[i] & 255;
+                const int64_t e = code[i] / (K * K);
+                const int ab = code[i] - static_cast<int>(e) * (K * K);
                 const int a = ab / K, bb = ab - a * K;
                 const int p = pair_index<K>(a, bb);
 #pragma unroll
@@ -429,6 +557,46 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             }
         return;
     }
+    if constexpr (E::d == 3 && E::p >= 3) {
+        // one wave per element; staged (also for a blocked request: no block
+        // schedule for orders above 2) or atomic
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        const unsigned grid = static_cast<unsigned>(std::min<int64_t>(m.T, 16384));
+        if (variant == LFEM_SCATTER_ATOMIC) {
+            for (int mat = 0; mat < NMAT; ++mat)
+                k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
+            with_rule<E>(m.Q, [&](auto qc) {
+                k_wave<E, decltype(qc)::value, NM, HA, true><<<grid, 64, 0, s>>>(g, m.T, m.conn, nullptr, p.row_ptr,
+                                                                                 p.off16);
+            });
+            LFEM_HIP(hipGetLastError());
+            return;
+        }
+        build_staged(m, p, s);
+        const size_t need = static_cast<size_t>(NMAT) * E::np * m.T * sizeof(double);
+        if (p.stage_bytes < need) {
+            dev_free(p.stage);
+            p.stage = nullptr;
+            p.stage_bytes = 0;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
+            p.stage_bytes = need;
+        }
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_wave<E, decltype(qc)::value, NM, HA, false><<<grid, 64, 0, s>>>(g, m.T, m.conn, p.stage, p.row_ptr,
+                                                                              p.off16);
+        });
+        LFEM_HIP(hipGetLastError());
+        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
+                                                                   o.v[1], o.v[2]);
+        LFEM_HIP(hipGetLastError());
+        if (p.nlong > 0) {
+            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
+                                                                             p.clist, p.stage, o.v[0], o.v[1],
+                                                                             o.v[2]);
+            LFEM_HIP(hipGetLastError());
+        }
+        return;
+    } else {
     if (variant == LFEM_SCATTER_ATOMIC) {
         for (int mat = 0; mat < NMAT; ++mat)
             k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
@@ -487,6 +655,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             throw Error{LFEM_EUNSUPPORTED, "side-slot schedule for a tetrahedral mesh"};
         }
         return launch_blocked<E, NM, HA, NT>(m, p, o, lds, s);
+    }
     }
 }
 

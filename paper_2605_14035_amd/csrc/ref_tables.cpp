@@ -312,18 +312,23 @@ const int EDGE_SEG[1][2] = {{0, 1}};
 const int EDGE_TRI[3][2] = {{0, 1}, {1, 2}, {2, 0}};
 const int EDGE_TET[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
 
-// Orders 3 and 4 (segments, triangles): node a is the lattice point alpha / p
-// (|alpha| = p), ordered vertices, then p - 1 nodes per edge (u, v) of the edge
-// list from u to v, then the interior nodes (p = 3: (1,1,1); p = 4: (2,1,1),
-// (1,2,1), (1,1,2)); its Lagrange function is
+// Orders 3 and 4: node a is the lattice point alpha / p (|alpha| = p),
+// ordered vertices, then p - 1 nodes per edge (u, v) of the edge list from u
+// to v, then on a tetrahedron the nodes inside its faces (0,1,2), (0,1,3),
+// (0,2,3), (1,2,3) (p = 3: the face centroid; p = 4: (2,1,1), (1,2,1),
+// (1,1,2) over the face's vertices), then the interior nodes (triangle:
+// p = 3 (1,1,1), p = 4 (2,1,1), (1,2,1), (1,1,2); tetrahedron, p = 4:
+// (1,1,1,1)); its Lagrange function is
 //   phi_alpha(l) = prod_j prod_{r < alpha_j} (p l_j - r) / (r + 1).
-int lattice_nodes(int d, int p, int (*alpha)[3])
+const int FACE_TET[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+
+int lattice_nodes(int d, int p, int (*alpha)[4])
 {
     int n = 0;
     for (int i = 0; i <= d; ++i, ++n)
         for (int j = 0; j <= d; ++j) alpha[n][j] = i == j ? p : 0;
-    const int ne = d == 1 ? 1 : 3;
-    const int(*E)[2] = d == 1 ? EDGE_SEG : EDGE_TRI;
+    const int ne = d == 1 ? 1 : (d == 2 ? 3 : 6);
+    const int(*E)[2] = d == 1 ? EDGE_SEG : (d == 2 ? EDGE_TRI : EDGE_TET);
     for (int s = 0; s < ne; ++s)
         for (int i = 1; i < p; ++i, ++n) {
             for (int j = 0; j <= d; ++j) alpha[n][j] = 0;
@@ -337,15 +342,28 @@ int lattice_nodes(int d, int p, int (*alpha)[3])
             if (p == 4) alpha[n][c] = 2;
         }
     }
+    if (d == 3) {
+        const int per_face = p == 3 ? 1 : 3;
+        for (int f = 0; f < 4; ++f)
+            for (int c = 0; c < per_face; ++c, ++n) {
+                for (int j = 0; j <= d; ++j) alpha[n][j] = 0;
+                for (int v = 0; v < 3; ++v) alpha[n][FACE_TET[f][v]] = 1;
+                if (p == 4) alpha[n][FACE_TET[f][c]] = 2;
+            }
+        if (p == 4) {
+            alpha[n][0] = alpha[n][1] = alpha[n][2] = alpha[n][3] = 1;
+            ++n;
+        }
+    }
     return n;
 }
 
 void eval_lattice(int d, int p, const double *l, const double (*dl)[3], double *phi, double *g)
 {
-    int alpha[15][3];
+    int alpha[35][4];
     const int k = lattice_nodes(d, p, alpha);
     for (int a = 0; a < k; ++a) {
-        double f[3], df[3];
+        double f[4], df[4];
         for (int j = 0; j <= d; ++j) {
             // f_j = prod_{r < alpha_j} (p l_j - r) / (r + 1) and its l_j-derivative
             double v = 1.0, dv = 0.0;
@@ -416,7 +434,7 @@ int default_rule(int d, int p)
 {
     if (d == 1) return p == 1 ? 2 : (p == 2 ? 3 : (p == 3 ? 5 : 6));
     if (d == 2) return p == 1 ? 3 : (p == 2 ? 6 : 16);
-    return p == 1 ? 4 : 11;
+    return p == 1 ? 4 : (p == 2 ? 11 : 35);
 }
 
 bool build_ref_table(int d, int p, int npts, RefTable &out)
@@ -433,7 +451,7 @@ bool build_ref_table(int d, int p, int npts, RefTable &out)
     out.data.assign(static_cast<size_t>(out.stride) * npts, 0.0);
     for (int q = 0; q < npts; ++q) {
         double *t = out.data.data() + static_cast<size_t>(q) * out.stride;
-        double phi[15], g[45];
+        double phi[35], g[105];
         eval_basis(d, p, r.pts[q].data(), phi, g);
         t[0] = r.w[q];
         for (int m = 0; m < d; ++m) t[1 + m] = r.pts[q][m];

@@ -118,7 +118,7 @@ __global__ void k_inc_fill(const int32_t *__restrict__ conn, int64_t kT, int64_t
     if (node < 0 || node >= N) return;
     const int64_t a = i / T, e = i - a * T;
     const int32_t pos = atomicAdd(&cursor[node], 1);
-    ne[ptr[node] + pos] = static_cast<int32_t>(e * 16 + a);
+    ne[ptr[node] + pos] = static_cast<int32_t>(e << kIncShift | a);
 }
 
 // sort every short list [ptr[i], ptr[i+1]) ascending (insertion sort)
@@ -151,11 +151,15 @@ __global__ void k_validate(const int32_t *__restrict__ conn, int64_t T, int k,
 // ---------------------------------------------------------------------------
 // rows: the sorted set of nodes sharing an element with node i
 // ---------------------------------------------------------------------------
+// one thread per row with an insertion-sorted buffer of RMAX entries in LDS:
+// elements of up to kMaxNodes8 nodes (byte slot maps) take 64 rows of 255,
+// larger ones 16 rows of kMaxRowWide
 constexpr int ROW_NT = 64;
 constexpr int ROW_MAX = 255;
+constexpr int ROW_NT_WIDE = 16;
 
-template <int FILL>
-__global__ __launch_bounds__(ROW_NT) void k_rows(int64_t N, int k, int64_t T,
+template <int FILL, int RMAX = ROW_MAX, int NTR = ROW_NT>
+__global__ __launch_bounds__(NTR) void k_rows(int64_t N, int k, int64_t T,
                                                  const int32_t *__restrict__ conn,
                                                  const int32_t *__restrict__ ne_ptr,
                                                  const int32_t *__restrict__ ne,
@@ -164,31 +168,31 @@ __global__ __launch_bounds__(ROW_NT) void k_rows(int64_t N, int k, int64_t T,
                                                  int32_t *__restrict__ col_idx,
                                                  int32_t *__restrict__ flags)
 {
-    __shared__ int32_t buf[ROW_MAX * ROW_NT];
+    __shared__ int32_t buf[RMAX * NTR];
     const int t = threadIdx.x;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * ROW_NT + t;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * NTR + t;
     if (i >= N) return;  // no barrier below
     int len = 0;
     bool overflow = false;
     for (int32_t s = ne_ptr[i]; s < ne_ptr[i + 1] && !overflow; ++s) {
-        const int64_t e = ne[s] >> 4;
+        const int64_t e = ne[s] >> kIncShift;
         for (int b = 0; b < k; ++b) {
             const int32_t j = conn[b * T + e];
             int lo = 0, hi = len;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (buf[mid * ROW_NT + t] < j)
+                if (buf[mid * NTR + t] < j)
                     lo = mid + 1;
                 else
                     hi = mid;
             }
-            if (lo < len && buf[lo * ROW_NT + t] == j) continue;
-            if (len == ROW_MAX) {
+            if (lo < len && buf[lo * NTR + t] == j) continue;
+            if (len == RMAX) {
                 overflow = true;
                 break;
             }
-            for (int r = len; r > lo; --r) buf[r * ROW_NT + t] = buf[(r - 1) * ROW_NT + t];
-            buf[lo * ROW_NT + t] = j;
+            for (int r = len; r > lo; --r) buf[r * NTR + t] = buf[(r - 1) * NTR + t];
+            buf[lo * NTR + t] = j;
             ++len;
         }
     }
@@ -197,7 +201,7 @@ __global__ __launch_bounds__(ROW_NT) void k_rows(int64_t N, int k, int64_t T,
         rowlen[i] = len;
     } else {
         const int32_t b = row_ptr[i];
-        for (int r = 0; r < len; ++r) col_idx[b + r] = buf[r * ROW_NT + t];
+        for (int r = 0; r < len; ++r) col_idx[b + r] = buf[r * NTR + t];
     }
 }
 
@@ -235,25 +239,60 @@ __global__ void k_offsets(int k, int64_t T, const int32_t *__restrict__ conn,
     for (int w = 0; w < kkp / 4; ++w) dst[w] = words[w];
 }
 
+// the same with 16-bit offsets (off16[e * k * k + a * k + b]), for large elements
+__global__ void k_offsets16(int k, int64_t T, const int32_t *__restrict__ conn,
+                            const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                            uint16_t *__restrict__ off16, int32_t *__restrict__ flags)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    for (int a = 0; a < k; ++a) {
+        const int32_t row = conn[a * T + e];
+        const int32_t beg = row_ptr[row], end = row_ptr[row + 1];
+        for (int b = 0; b < k; ++b) {
+            const int32_t col = conn[b * T + e];
+            int32_t lo = beg, hi = end;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (col_idx[mid] < col)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo >= end || col_idx[lo] != col) atomicOr(&flags[3], 1);
+            off16[(e * k + a) * k + b] = static_cast<uint16_t>(lo - beg);
+        }
+    }
+}
+
+// column offset of local pair (a, b) of element e in row conn[a]: byte map
+// (stride kkp) or 16-bit map (stride k * k)
+__device__ __forceinline__ int32_t slot_offset(const uint8_t *off8, const uint16_t *off16, int kkp, int k,
+                                               int64_t e, int ab)
+{
+    return off16 ? static_cast<int32_t>(off16[e * k * k + ab]) : static_cast<int32_t>(off8[e * kkp + ab]);
+}
+
 // ---------------------------------------------------------------------------
 // staged scatter: slot -> contributions
 // ---------------------------------------------------------------------------
 __global__ void k_contrib_count(int k, int64_t T, const int32_t *__restrict__ conn,
                                 const int32_t *__restrict__ row_ptr,
                                 const uint8_t *__restrict__ off8, int kkp,
-                                int32_t *__restrict__ cnt)
+                                int32_t *__restrict__ cnt, const uint16_t *__restrict__ off16 = nullptr)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= T) return;
     for (int a = 0; a < k; ++a) {
         const int32_t rb = row_ptr[conn[a * T + e]];
-        for (int b = 0; b < k; ++b) atomicAdd(&cnt[rb + off8[e * kkp + a * k + b]], 1);
+        for (int b = 0; b < k; ++b) atomicAdd(&cnt[rb + slot_offset(off8, off16, kkp, k, e, a * k + b)], 1);
     }
 }
 
+// contribution codes e * k * k + a * k + b (the host checks k * k * T < 2^31)
 __global__ void k_contrib_fill(int k, int64_t T, const int32_t *__restrict__ conn,
                                const int32_t *__restrict__ row_ptr,
-                               const uint8_t *__restrict__ off8, int kkp,
+                               const uint8_t *__restrict__ off8, const uint16_t *__restrict__ off16, int kkp,
                                const int32_t *__restrict__ cptr, int32_t *__restrict__ cursor,
                                int32_t *__restrict__ clist)
 {
@@ -262,9 +301,9 @@ __global__ void k_contrib_fill(int k, int64_t T, const int32_t *__restrict__ con
     for (int a = 0; a < k; ++a) {
         const int32_t rb = row_ptr[conn[a * T + e]];
         for (int b = 0; b < k; ++b) {
-            const int32_t slot = rb + off8[e * kkp + a * k + b];
+            const int32_t slot = rb + slot_offset(off8, off16, kkp, k, e, a * k + b);
             const int32_t pos = atomicAdd(&cursor[slot], 1);
-            clist[cptr[slot] + pos] = static_cast<int32_t>(e * 256 + a * k + b);  // a*k + b < 256
+            clist[cptr[slot] + pos] = static_cast<int32_t>((e * k + a) * k + b);
         }
     }
 }
@@ -415,9 +454,15 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
     LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&rowlen), (m.N + 1) * sizeof(int32_t), s));
     LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&tot), sizeof(int64_t), s));
     p.row_ptr = dev_alloc<int32_t>(m.N + 1);
+    const bool wide = m.k > kMaxNodes8;
+    const int row_cap = wide ? kMaxRowWide : ROW_MAX;
     if (m.N > 0) {
-        k_rows<0><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne,
-                                                           rowlen, nullptr, nullptr, m.flags);
+        if (wide)
+            k_rows<0, kMaxRowWide, ROW_NT_WIDE><<<grid_for(m.N, ROW_NT_WIDE), ROW_NT_WIDE, 0, s>>>(
+                m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen, nullptr, nullptr, m.flags);
+        else
+            k_rows<0><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen,
+                                                               nullptr, nullptr, m.flags);
         LFEM_HIP(hipGetLastError());
     }
     exclusive_scan_i32(rowlen, p.row_ptr, m.N, tot, s);
@@ -427,23 +472,38 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
     LFEM_HIP(hipStreamSynchronize(s));
     LFEM_HIP(hipFreeAsync(rowlen, s));
     LFEM_HIP(hipFreeAsync(tot, s));
-    LFEM_REQUIRE(!flags[2], LFEM_ERANGE, "a CSR row would hold more than 255 entries");
+    LFEM_REQUIRE(!flags[2], LFEM_ERANGE,
+                 row_cap == ROW_MAX ? "a CSR row would hold more than 255 entries"
+                                    : "a CSR row would hold more than 1023 entries");
     LFEM_REQUIRE(nnz < (int64_t(1) << 31), LFEM_ERANGE, "nnz does not fit in int32");
     p.nnz = nnz;
     p.col_idx = dev_alloc<int32_t>(nnz);
     if (m.N > 0) {
-        k_rows<1><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne,
-                                                           nullptr, p.row_ptr, p.col_idx, m.flags);
+        if (wide)
+            k_rows<1, kMaxRowWide, ROW_NT_WIDE><<<grid_for(m.N, ROW_NT_WIDE), ROW_NT_WIDE, 0, s>>>(
+                m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, nullptr, p.row_ptr, p.col_idx, m.flags);
+        else
+            k_rows<1><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, nullptr,
+                                                               p.row_ptr, p.col_idx, m.flags);
         LFEM_HIP(hipGetLastError());
     }
     p.kkp = (m.k * m.k + 3) / 4 * 4;
-    LFEM_REQUIRE(m.k <= kMaxNodes && p.kkp / 4 <= kMaxSlotWords, LFEM_EUNSUPPORTED,
-                 "element has more nodes than the slot map holds");
-    p.off8 = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * m.T);
-    if (m.T > 0) {
-        k_offsets<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.col_idx, p.off8,
-                                                     p.kkp, m.flags);
-        LFEM_HIP(hipGetLastError());
+    LFEM_REQUIRE(m.k <= kMaxNodes, LFEM_EUNSUPPORTED, "element has more nodes than the slot map holds");
+    if (wide) {
+        p.off16 = dev_alloc<uint16_t>(static_cast<size_t>(m.k) * m.k * m.T);
+        if (m.T > 0) {
+            k_offsets16<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.col_idx, p.off16,
+                                                           m.flags);
+            LFEM_HIP(hipGetLastError());
+        }
+    } else {
+        LFEM_REQUIRE(p.kkp / 4 <= kMaxSlotWords, LFEM_EUNSUPPORTED, "element has more nodes than the slot map holds");
+        p.off8 = dev_alloc<uint8_t>(static_cast<size_t>(p.kkp) * m.T);
+        if (m.T > 0) {
+            k_offsets<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.col_idx, p.off8,
+                                                         p.kkp, m.flags);
+            LFEM_HIP(hipGetLastError());
+        }
     }
     // host copies for the block schedule
     p.h_row_ptr.resize(m.N + 1);
@@ -472,8 +532,8 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
 void build_staged(Mesh &m, Pattern &p, hipStream_t s)
 {
     if (p.cptr) return;
-    LFEM_REQUIRE(m.T < (int64_t(1) << 23), LFEM_EUNSUPPORTED,
-                 "staged scatter supports fewer than 2^23 elements");
+    LFEM_REQUIRE(static_cast<int64_t>(m.k) * m.k * m.T < (int64_t(1) << 31), LFEM_EUNSUPPORTED,
+                 "staged scatter supports fewer than 2^31 / k^2 elements");
     const int64_t kkT = static_cast<int64_t>(m.k) * m.k * m.T;
     int32_t *cnt = nullptr;
     int64_t *tot = nullptr;
@@ -484,13 +544,13 @@ void build_staged(Mesh &m, Pattern &p, hipStream_t s)
     LFEM_HIP(hipMemsetAsync(cnt, 0, (p.nnz + 1) * sizeof(int32_t), s));
     if (m.T > 0) {
         k_contrib_count<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.off8,
-                                                           p.kkp, cnt);
+                                                           p.kkp, cnt, p.off16);
         LFEM_HIP(hipGetLastError());
     }
     exclusive_scan_i32(cnt, p.cptr, p.nnz, tot, s);
     LFEM_HIP(hipMemsetAsync(cnt, 0, (p.nnz + 1) * sizeof(int32_t), s));
     if (m.T > 0) {
-        k_contrib_fill<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.off8,
+        k_contrib_fill<<<grid_for(m.T, 256), 256, 0, s>>>(m.k, m.T, m.conn, p.row_ptr, p.off8, p.off16,
                                                           p.kkp, p.cptr, cnt, p.clist);
         LFEM_HIP(hipGetLastError());
     }
@@ -622,7 +682,7 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
             if (rp[r1 + 1] - rp[r0] + slots + add > cap) break;
             const size_t before = list.size();
             for (int32_t q = p.h_ne_ptr[r1]; q < p.h_ne_ptr[r1 + 1]; ++q) {
-                const int32_t e = p.h_ne[q] >> 4;
+                const int32_t e = p.h_ne[q] >> kIncShift;
                 if (stamp[e] != nb) {
                     stamp[e] = nb;
                     list.push_back(e);

@@ -24,6 +24,7 @@ from meshgen import meshes as mg
 pytestmark = pytest.mark.gpu
 
 TYPES = [(dom, d, p) for (dom, d) in (("surface", 1), ("surface", 2), ("bulk", 2)) for p in (3, 4)]
+TET_TYPES = [("bulk", 3, 3), ("bulk", 3, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -52,6 +53,15 @@ def order_mesh(domain, d, p, seed=0):
         V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
         V = mg.normalize_rows(V) * (1.0 + 0.05 * rng.uniform(-1, 1, size=len(V)))[:, None]
         quad = 16
+    elif domain == "bulk" and d == 3:
+        V, F, _ = mg.kuhn_cube(2, order=1)
+        V, F = mg.p1_to_pp(V, F, p, mg.TET_EDGES)
+        # every non-vertex node inside the cube moved by a twentieth of the node
+        # spacing h / p (h = 1/2; a tenth folds Kuhn quartics): curved elements
+        inter = np.all((V > 1e-12) & (V < 1 - 1e-12), axis=1)
+        amp = 0.05 / (2 * p)
+        V[inter] += rng.uniform(-amp, amp, size=(int(inter.sum()), 3))
+        quad = 35
     else:
         V, F = mg.square_tri(3)
         V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
@@ -64,17 +74,20 @@ def order_mesh(domain, d, p, seed=0):
     coords, conn = mg.to_soa(V, F)
     if domain == "bulk":
         # every element valid: det J of one sign at points spread over the element
-        xi = np.array([(i / 8, j / 8) for i in range(9) for j in range(9 - i)])
+        if d == 2:
+            xi = np.array([(i / 8, j / 8) for i in range(9) for j in range(9 - i)])
+        else:
+            xi = np.array([(i / 6, j / 6, l / 6) for i in range(7) for j in range(7 - i) for l in range(7 - i - j)])
         for e in range(conn.shape[1]):
             x = coords[:, conn[:, e]]
-            dets = [np.linalg.det(x @ oracle.basis(2, p, pt)[1]) for pt in xi]
+            dets = [np.linalg.det(x @ oracle.basis(d, p, pt)[1]) for pt in xi]
             assert min(dets) > 0 or max(dets) < 0, f"folded element {e}"
     N = coords.shape[1]
     return dict(domain=domain, dim=d, order=p, quad=quad, coords=coords, conn=conn,
                 coef_a=rng.uniform(0.5, 2.0, size=N), coef_c=rng.uniform(0.5, 2.0, size=N))
 
 
-@pytest.mark.parametrize("t", TYPES)
+@pytest.mark.parametrize("t", TYPES + TET_TYPES)
 @pytest.mark.parametrize("variant", ["auto", "blocked", "staged", "atomic"])
 def test_matrices(lf, t, variant):
     m = order_mesh(*t)
@@ -147,4 +160,57 @@ def test_rules_and_batch_limits(lf):
     out = dm.assemble(lf.LFEM_M)
     rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
     assert_csr_close(rp, ci, out["M"].cpu().numpy(), oracle.assemble(m, "mass"), what="default rule")
+    dm.close()
+
+
+@pytest.mark.parametrize("t", TET_TYPES)
+def test_tetrahedra_other_calls_unsupported(lf, t):
+    """Tetrahedra of orders 3 and 4 assemble matrices (above); the load vector,
+    the mean-curvature-flow terms and the shape gradient are not built for
+    them and say so."""
+    m = order_mesh(*t)
+    dm = lf.DeviceMesh.from_dict(m)
+    x = torch.ones(dm.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(lf.LfemError) as e:
+        dm.load(x)
+    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    g = torch.empty_like(dm.coords)
+    with pytest.raises(lf.LfemError) as e:
+        lf.lfem_shape_grad(dm.handle, x, x, 1.0, None, None, 0.0, g)
+    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    dm.close()
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_tetrahedra_larger_cube_sampled(lf, p):
+    """Order-p tetrahedra on an 8^3 Kuhn cube (3,072 elements; 15,625 / 35,937
+    nodes), M and A_a: sampled rows against the oracle, 1^T M 1 = 1, A 1 = 0
+    row by row, and the same bits on a second call."""
+    V, F, _ = mg.kuhn_cube(8, order=1)
+    V, F = mg.p1_to_pp(V, F, p, mg.TET_EDGES)
+    V, F, _ = mg.sfc_reorder(V, F)
+    coords, conn = mg.to_soa(V, F)
+    N = coords.shape[1]
+    a = 1.0 + 0.5 * np.sin(2 * np.pi * coords[0]) * np.cos(2 * np.pi * coords[1]) * coords[2]
+    m = dict(domain="bulk", dim=3, order=p, quad=35, coords=coords, conn=conn)
+    say("order", p, "tetrahedra, 8^3 cube:", conn.shape, N)
+    dm = lf.DeviceMesh.from_dict(m)
+    ca = torch.as_tensor(a, device="cuda")
+    out = dm.assemble(lf.LFEM_M | lf.LFEM_A, coef_a=ca)
+    again = dm.assemble(lf.LFEM_M | lf.LFEM_A, coef_a=ca)
+    assert torch.equal(out["M"], again["M"]) and torch.equal(out["A"], again["A"])
+    assert abs(float(out["M"].sum().item()) - 1.0) <= 1e-12
+    rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
+    Av = out["A"].cpu().numpy()
+    rows_of = np.repeat(np.arange(N), np.diff(rp))
+    rs = np.zeros(N)
+    np.add.at(rs, rows_of, Av)
+    amax = np.zeros(N)
+    np.maximum.at(amax, rows_of, np.abs(Av))
+    assert float((np.abs(rs) / amax).max()) <= 1e-12
+    from gpu_util import assert_rows_close
+    rows = np.unique(np.random.default_rng(40 + p).integers(0, N, 60))
+    for key, kind, c in (("M", "mass", None), ("A", "stiffness", a)):
+        ref = oracle.assemble(m, kind, coef=c, rows=rows)
+        assert_rows_close(rp, ci, out[key].cpu().numpy(), ref, rows, what=f"P{p} tets {key}")
     dm.close()
