@@ -262,31 +262,54 @@ lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what
                                   int *variant_out);
 
 /*
- * Batched assembly: many meshes of uneven size assembled in one persistent
- * launch replayed from a HIP graph.  Covered: curves, surfaces and planar
- * domains of order 1 or 2 under their two default rules (segment 2 or 3
- * points, triangle 3 or 6 points), whose patterns carry a side-slot block
- * schedule.  what: matrices per mesh (LFEM_M | LFEM_A; coefficients are not
- * supported in batches).  Other meshes (tetrahedra, orders 3 and 4, the
- * high-order rules): LFEM_EUNSUPPORTED.  autotune != 0 times the candidate
- * block capacities once at creation and rebuilds the patterns' schedules
- * (SYNCHRONISES stream).  The handle keeps the mesh and pattern handles
- * (which must outlive it).
+ * Batched assembly (section 6.1's many-meshes workload): n meshes of uneven
+ * size assembled by one HIP graph replay.  Any mesh and rule the library
+ * assembles may be a member:
+ *   - curves, surfaces and planar domains of order 1 or 2 under their two
+ *     default rules (segment 2 or 3 points, triangle 3 or 6 points), whose
+ *     patterns carry a side-slot block schedule, without coefficients and
+ *     without LFEM_MC, share one persistent launch (work items = (mesh, row
+ *     block) pairs, largest first, pulled from an atomic counter);
+ *   - every other member (tetrahedra, orders 3 and 4, high-order rules, a
+ *     coefficient, the weighted mass) is assembled by its own numeric launch
+ *     with its pattern's tuned scatter, recorded into the same graph.
+ * Results equal lfem_assemble with LFEM_SCATTER_AUTO on each mesh bitwise.
+ * what: matrices per mesh, any non-empty combination of LFEM_M, LFEM_A,
+ * LFEM_MC.  autotune != 0 times the candidate block capacities of the
+ * persistent kernel's members once at creation and rebuilds their schedules
+ * (SYNCHRONISES stream).  Creation also runs each other member once on
+ * scratch outputs to build its lazily created structures (SYNCHRONISES).
+ * The handle keeps the mesh and pattern handles (which must outlive it).
  */
 lfem_status lfem_batch_create(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
                               unsigned what, int autotune, void *stream, lfem_batch_t *out);
 
 /*
+ * lfem_batch_create with nodal coefficients: coef_a[i] (may be NULL, or the
+ * whole array NULL) is mesh i's device array of N_i doubles, the coefficient
+ * a_h inside A (section 3.2); coef_c[i] the weight c_h of M_c, required for
+ * every mesh with elements when what contains LFEM_MC (else LFEM_EINVAL).
+ * The pointers are kept by the batch and read at every replay (their values
+ * may change between calls; the arrays must outlive the batch).
+ */
+lfem_status lfem_batch_create_ex(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
+                                 unsigned what, const double *const *coef_a, const double *const *coef_c,
+                                 int autotune, void *stream, lfem_batch_t *out);
+
+/*
  * Run the batch.  vals[i * nmat + j] is the output of matrix j of mesh i,
- * nmat = number of bits in `what`, ordered M then A; each has that mesh's
+ * nmat = number of bits in `what`, ordered M, A, MC; each has that mesh's
  * nnz doubles and is overwritten.  Each call reads every mesh's current
  * coordinates (lfem_mesh_set_coords).  When the output or coordinate pointers
- * differ from the previous call the library waits for the previous upload to
- * finish before updating its device-side pointer table.  If a pattern's block
- * schedule was rebuilt since the batch was set up (lfem_pattern_autotune,
- * another batch's autotuning), the call SYNCHRONISES stream and rebuilds the
- * batch's work list and graph first (LFEM_EUNSUPPORTED if the new schedule
- * is not one the batch kernel runs).
+ * of a persistent-kernel member differ from the previous call the library
+ * waits for the previous descriptor upload before updating its device-side
+ * pointer table; when those of another member (or its pattern's staging
+ * buffer) differ from the graph's, the call SYNCHRONISES stream and captures
+ * the graph again.  If a pattern's block schedule was rebuilt since the batch
+ * was set up (lfem_pattern_autotune, another batch's autotuning), the call
+ * SYNCHRONISES stream and rebuilds the work list and graph first; a member
+ * whose new schedule the persistent kernel does not run gets a launch of its
+ * own.  Calls of one batch that overlap on different streams race.
  */
 lfem_status lfem_assemble_batch(lfem_batch_t b, double *const *vals, void *stream);
 

@@ -28,7 +28,7 @@ __all__ = [
     "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LfemError",
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
-    "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
+    "lfem_pattern_autotune", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
     "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
@@ -163,8 +163,32 @@ def lfem_batch_create(meshes, patterns, what: int, autotune: int = 0, stream=Non
     return out
 
 
+def lfem_batch_create_ex(meshes, patterns, what: int, coef_a=None, coef_c=None, autotune: int = 0,
+                         stream=None):
+    """coef_a / coef_c: None or a list (one entry per mesh) of float64 device
+    tensors (N_i,) or None; the batch keeps their pointers, so the caller keeps
+    the tensors alive for the batch's lifetime."""
+    n = len(meshes)
+    ms = (C.c_void_p * n)(*[m.value for m in meshes])
+    ps = (C.c_void_p * n)(*[p.value for p in patterns])
+
+    def arr(cs, name):
+        if cs is None:
+            return None
+        if len(cs) != n:
+            raise ValueError(f"{name} needs one entry per mesh")
+        return (C.c_void_p * n)(*[(_ptr(c, torch.float64, name).value if c is not None else None)
+                                  for c in cs])
+
+    out = C.c_void_p()
+    _lib.check(_L.lfem_batch_create_ex(n, ms, ps, int(what), arr(coef_a, "coef_a"), arr(coef_c, "coef_c"),
+                                       int(autotune), _stream(stream), C.byref(out)), "lfem_batch_create_ex")
+    return out
+
+
 def lfem_assemble_batch(batch, vals, stream=None):
-    """vals: flat list of float64 device tensors, mesh-major, M before A."""
+    """vals: flat list of float64 device tensors, mesh-major, ordered M, A, MC
+    within a mesh."""
     arr = (C.c_void_p * len(vals))(*[_ptr(v, torch.float64, "vals").value for v in vals])
     _lib.check(_L.lfem_assemble_batch(batch, arr, _stream(stream)), "lfem_assemble_batch")
 

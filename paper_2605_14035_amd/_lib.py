@@ -39,7 +39,7 @@ EXPORTS = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info",
     "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
-    "lfem_pattern_autotune", "lfem_batch_create", "lfem_assemble_batch", "lfem_shape_grad",
+    "lfem_pattern_autotune", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
     "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy",
 ]
@@ -83,6 +83,7 @@ def load():
     L.lfem_assemble_weighted.argtypes = [vp, vp, vp, vp, vp]
     L.lfem_pattern_autotune.argtypes = [vp, vp, cu, vp, C.POINTER(ci)]
     L.lfem_batch_create.argtypes = [ci, vpp, vpp, cu, ci, vp, vpp]
+    L.lfem_batch_create_ex.argtypes = [ci, vpp, vpp, cu, vpp, vpp, ci, vp, vpp]
     L.lfem_assemble_batch.argtypes = [vp, vpp, vp]
     L.lfem_shape_grad.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, vp, vp]
     L.lfem_shape_grad_noalloc.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, vp, vp]

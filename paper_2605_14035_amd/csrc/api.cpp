@@ -30,7 +30,8 @@ struct lfem_pattern_s : Pattern {};
 namespace lfem {
 // batch.hip
 lfem_status batch_create(int n, Mesh *const *meshes, Pattern *const *pats, unsigned what,
-                         int autotune, hipStream_t s, lfem_batch_t *out);
+                         const double *const *coef_a, const double *const *coef_c, int autotune,
+                         hipStream_t s, lfem_batch_t *out);
 void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s);
 void batch_destroy(lfem_batch_t b);
 // tune.cpp
@@ -333,23 +334,32 @@ lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what
     });
 }
 
-lfem_status lfem_batch_create(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
-                              unsigned what, int autotune, void *stream, lfem_batch_t *out)
+lfem_status lfem_batch_create_ex(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
+                                 unsigned what, const double *const *coef_a, const double *const *coef_c,
+                                 int autotune, void *stream, lfem_batch_t *out)
 {
     lfem_status st = LFEM_OK;
     lfem_status g = guarded([&] {
         LFEM_REQUIRE(out && n > 0 && meshes && pats, LFEM_EINVAL, "bad batch arguments");
+        *out = nullptr;
         std::vector<Mesh *> ms(n);
         std::vector<Pattern *> ps(n);
         for (int i = 0; i < n; ++i) {
             LFEM_REQUIRE(meshes[i] && pats[i] && pats[i]->mesh == meshes[i], LFEM_EINVAL,
                          "batch entry with a null or mismatched mesh/pattern");
+            LFEM_REQUIRE(meshes[i]->coords || meshes[i]->N == 0, LFEM_EINVAL, "mesh has no coordinates");
             ms[i] = meshes[i];
             ps[i] = pats[i];
         }
-        st = batch_create(n, ms.data(), ps.data(), what, autotune, S(stream), out);
+        st = batch_create(n, ms.data(), ps.data(), what, coef_a, coef_c, autotune, S(stream), out);
     });
     return g != LFEM_OK ? g : st;
+}
+
+lfem_status lfem_batch_create(int n, const lfem_mesh_t *meshes, const lfem_pattern_t *pats,
+                              unsigned what, int autotune, void *stream, lfem_batch_t *out)
+{
+    return lfem_batch_create_ex(n, meshes, pats, what, nullptr, nullptr, autotune, stream, out);
 }
 
 lfem_status lfem_assemble_batch(lfem_batch_t b, double *const *vals, void *stream)

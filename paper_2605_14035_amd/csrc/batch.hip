@@ -1,17 +1,21 @@
-// Batched assembly of many meshes of uneven size in one persistent launch.
+// Batched assembly of many meshes of uneven size, replayed from one HIP graph.
 //
-// Every (mesh, row block) pair of the batch is a work item; items are sorted by
-// cost (block element count, largest first).  A persistent grid of as many
-// workgroups as fit on the device at once pulls items from an atomic counter,
-// so large and small meshes share the machine without a launch per mesh.  The
-// counter reset and the persistent kernel are captured once into a HIP graph;
-// each lfem_assemble_batch call replays it.  Per-mesh arguments (including the
-// output pointers) live in a device descriptor array that is rewritten only
-// when the caller's output pointers change.
+// Meshes of the persistent kernel's family (curves, surfaces and planar meshes
+// of order 1 or 2 under their default rules, whose patterns carry a side-slot
+// block schedule, assembling plain M and A) share one persistent launch: every
+// (mesh, row block) pair is a work item, items are sorted by cost (block
+// element count, largest first), and a grid of as many workgroups as fit on
+// the device at once pulls items from an atomic counter, so large and small
+// meshes share the machine without a launch per mesh.  Their per-mesh
+// arguments (output and coordinate pointers included) live in a device
+// descriptor table rewritten only when those pointers change.
 //
-// The batch kernel covers the mesh families whose many-contribution entries are
-// diagonal (curves, surfaces, planar meshes: the side-slot form of the blocked
-// scatter); meshes outside that family are rejected.
+// Every other member (nodal coefficients, the weighted mass, the high-order
+// rules, orders 3 and 4, tetrahedra) is assembled by its own numeric launch
+// with its pattern's tuned scatter, recorded into the same graph after the
+// persistent kernel.  The graph is captured again when an output, coordinate
+// or staging pointer of such a member changes.  One replay assembles the
+// whole batch.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -26,6 +30,10 @@ struct lfem_batch_s {
     int nmat = 0;
     std::vector<lfem::Mesh *> meshes;
     std::vector<lfem::Pattern *> pats;
+    std::vector<const double *> coef_a, coef_c;  // per mesh, null for none
+    std::vector<char> fast;                      // assembled by the persistent kernel
+    int nfast = 0;
+    // persistent kernel
     std::vector<lfem::BlockArgs> host_desc;
     lfem::BlockArgs *pinned = nullptr;  // staging for descriptor uploads
     lfem::BlockArgs *desc = nullptr;    // device descriptors
@@ -36,15 +44,20 @@ struct lfem_batch_s {
     int dump = 0;  // first LDS dump entry (= largest block capacity)
     int rs = 0;    // doubles of one LDS matrix region
     int grid = 0;
-    hipStream_t capture = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     hipEvent_t upload_done = nullptr;
     bool uploaded = false;
     std::vector<double *> last_vals;
     std::vector<const double *> last_coords;
     std::vector<uint64_t> gens;  // schedule generation of each pattern at prepare()
     int cap = 0;
+    // the graph and the pointers its per-member launches were captured with
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool captured = false;
+    std::vector<double *> cap_vals;
+    std::vector<const double *> cap_coords;
+    std::vector<const double *> cap_stage;
 };
 
 namespace lfem {
@@ -117,11 +130,13 @@ BatchKernel pick_kernel(unsigned what)
     return k_batch<1, true>;
 }
 
+// a mesh the persistent kernel runs: orders 1 and 2 of curves, surfaces and
+// planar meshes under the two default rules of each dimension, with a
+// side-slot block schedule
 bool batch_eligible(const Mesh &m, const Pattern &p)
 {
-    // the batch kernel is compiled for the two default rules of each dimension
     const bool rule_ok = m.Q == (m.d == 1 ? 2 : 3) || m.Q == (m.d == 1 ? 3 : 6);
-    return m.d <= 2 && rule_ok && (m.T == 0 || (p.sched.nb > 0 && p.sched.side_mode));
+    return m.d <= 2 && m.p <= 2 && rule_ok && (m.T == 0 || (p.sched.nb > 0 && p.sched.side_mode));
 }
 
 void release_graph(lfem_batch_s &b)
@@ -130,10 +145,13 @@ void release_graph(lfem_batch_s &b)
     if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
+    b.captured = false;
 }
 
-// (re)build descriptors, work list, launch shape and the captured graph
-void prepare(lfem_batch_s &b, hipStream_t s)
+// (re)build the persistent kernel's descriptors, work list and launch shape
+// over the members it runs; drops the graph (captured again before the next
+// replay)
+void prepare(lfem_batch_s &b)
 {
     release_graph(b);
     dev_free(b.desc);
@@ -141,13 +159,21 @@ void prepare(lfem_batch_s &b, hipStream_t s)
     b.desc = nullptr;
     b.items = nullptr;
     b.host_desc.clear();
+    b.n_items = 0;
+    b.uploaded = false;
+    b.last_vals.clear();
+    b.last_coords.clear();
+    b.gens.resize(b.n);
+    for (int i = 0; i < b.n; ++i) b.gens[i] = b.pats[i]->sched_gen;
+    if (b.nfast == 0) return;
     std::vector<std::pair<int, int2>> work;  // (cost, item)
     int max_cap = 1, max_row = 0;
     for (int i = 0; i < b.n; ++i) {
         Mesh &m = *b.meshes[i];
         Pattern &p = *b.pats[i];
-        b.host_desc.push_back(block_args(m, p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
-        if (m.T == 0) continue;
+        b.host_desc.push_back(b.fast[i] ? block_args(m, p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)
+                                        : BlockArgs{});
+        if (!b.fast[i] || m.T == 0) continue;
         max_cap = std::max(max_cap, p.sched.cap);
         max_row = std::max(max_row, p.max_row);
         std::vector<int32_t> ep(p.sched.nb + 1);
@@ -187,23 +213,117 @@ void prepare(lfem_batch_s &b, hipStream_t s)
                                                           BATCH_NT, b.lds));
     LFEM_REQUIRE(per_cu > 0, LFEM_EUNSUPPORTED, "batch kernel does not fit on a compute unit");
     b.grid = std::max(1, std::min(per_cu * prop.multiProcessorCount, std::max(1, b.n_items)));
-    // capture: counter reset (a kernel, not a memset node) + persistent kernel
+}
+
+// numeric launch arguments of member i writing into vals[i * nmat ...]
+// (ordered M, A, MC)
+NumericOut member_out(const lfem_batch_s &b, int i, double *const *vals)
+{
+    NumericOut o;
+    o.what = b.what;
+    o.coef_a = b.coef_a[i];
+    o.coef_c = b.coef_c[i];
+    double *const *v = vals + static_cast<size_t>(i) * b.nmat;
+    int j = 0;
+    if (b.what & LFEM_M) o.vals_m = v[j++];
+    if (b.what & LFEM_A) o.vals_a = v[j++];
+    if (b.what & LFEM_MC) o.vals_mc = v[j++];
+    return o;
+}
+
+// the scatter a member is launched with: its pattern's tuned variant (staged
+// when it has no block schedule)
+int member_variant(const lfem_batch_s &b, int i)
+{
+    const Pattern &p = *b.pats[i];
+    int v = p.tuned_variant;
+    if (v == LFEM_SCATTER_BLOCKED && p.sched.nb == 0 && b.meshes[i]->T > 0) v = LFEM_SCATTER_STAGED;
+    return v;
+}
+
+// one launch of every member outside the persistent kernel, on scratch
+// outputs, outside any capture: builds the structures a launch creates on
+// first use (contribution lists, staging buffer), which must not be
+// allocated while the graph is being captured (SYNCHRONISES s)
+void warm_members(lfem_batch_s &b, hipStream_t s)
+{
+    std::vector<double *> scratch;
+    try {
+        for (int i = 0; i < b.n; ++i) {
+            if (b.fast[i] || b.meshes[i]->T == 0) continue;
+            std::vector<double *> all(static_cast<size_t>(b.n) * b.nmat, nullptr);
+            for (int j = 0; j < b.nmat; ++j) {
+                double *v = nullptr;
+                LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&v), std::max<int64_t>(b.pats[i]->nnz, 1) * 8));
+                scratch.push_back(v);
+                all[static_cast<size_t>(i) * b.nmat + j] = v;
+            }
+            launch_numeric(*b.meshes[i], *b.pats[i], member_out(b, i, all.data()), member_variant(b, i), s);
+        }
+        LFEM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        for (double *v : scratch) dev_free(v);
+        throw;
+    }
+    for (double *v : scratch) dev_free(v);
+}
+
+// capture the graph: counter reset (a kernel, not a memset node) and the
+// persistent kernel, then, unless fast_only, one numeric launch per other
+// member with the given outputs and its current coordinates
+void capture_graph(lfem_batch_s &b, double *const *vals, bool fast_only)
+{
+    release_graph(b);
     LFEM_HIP(hipStreamBeginCapture(b.capture, hipStreamCaptureModeThreadLocal));
-    k_zero_int<<<1, 1, 0, b.capture>>>(b.counter);
-    kern<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter, b.dump, b.rs);
     hipGraph_t g = nullptr;
-    const hipError_t e1 = hipGetLastError();
-    const hipError_t e2 = hipStreamEndCapture(b.capture, &g);
-    LFEM_HIP(e1);
-    LFEM_HIP(e2);
+    try {
+        if (b.nfast > 0) {
+            k_zero_int<<<1, 1, 0, b.capture>>>(b.counter);
+            pick_kernel(b.what)<<<b.grid, BATCH_NT, b.lds, b.capture>>>(b.desc, b.items, b.n_items, b.counter,
+                                                                        b.dump, b.rs);
+            LFEM_HIP(hipGetLastError());
+        }
+        if (!fast_only)
+            for (int i = 0; i < b.n; ++i)
+                if (!b.fast[i])
+                    launch_numeric(*b.meshes[i], *b.pats[i], member_out(b, i, vals), member_variant(b, i),
+                                   b.capture);
+    } catch (...) {
+        (void)hipStreamEndCapture(b.capture, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    LFEM_HIP(hipStreamEndCapture(b.capture, &g));
     b.graph = g;
     LFEM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-    b.uploaded = false;
-    b.last_vals.clear();
-    b.last_coords.clear();
-    b.gens.resize(b.n);
-    for (int i = 0; i < b.n; ++i) b.gens[i] = b.pats[i]->sched_gen;
-    (void)s;
+    if (fast_only) return;
+    b.captured = true;
+    b.cap_vals.assign(vals, vals + static_cast<size_t>(b.n) * b.nmat);
+    b.cap_coords.resize(b.n);
+    b.cap_stage.resize(b.n);
+    for (int i = 0; i < b.n; ++i) {
+        b.cap_coords[i] = b.meshes[i]->coords;
+        b.cap_stage[i] = b.pats[i]->stage;
+    }
+}
+
+// true when the graph must be captured again: none yet, or an output,
+// coordinate or staging-buffer pointer of a member outside the persistent
+// kernel differs from the captured one (another assembly on the same
+// pattern may have reallocated its staging buffer)
+bool members_moved(const lfem_batch_s &b, double *const *vals)
+{
+    if (!b.captured) return true;
+    for (int i = 0; i < b.n; ++i) {
+        if (b.fast[i]) continue;
+        if (b.meshes[i]->coords != b.cap_coords[i] || b.pats[i]->stage != b.cap_stage[i]) return true;
+        for (int j = 0; j < b.nmat; ++j) {
+            const size_t k = static_cast<size_t>(i) * b.nmat + j;
+            if (vals[k] != b.cap_vals[k]) return true;
+        }
+    }
+    return false;
 }
 
 // The descriptor table holds the output pointers and each mesh's current
@@ -211,6 +331,7 @@ void prepare(lfem_batch_s &b, hipStream_t s)
 // when either set differs from the last upload.
 void upload_descriptors(lfem_batch_s &b, double *const *vals, hipStream_t s)
 {
+    if (b.nfast == 0) return;
     std::vector<double *> cur(vals, vals + static_cast<size_t>(b.n) * b.nmat);
     std::vector<const double *> xs(b.n);
     for (int i = 0; i < b.n; ++i) xs[i] = b.meshes[i]->coords;
@@ -237,6 +358,7 @@ float time_batch(lfem_batch_s &b, const std::vector<double *> &vals, hipStream_t
     LFEM_HIP(hipEventCreate(&e0));
     LFEM_HIP(hipEventCreate(&e1));
     upload_descriptors(b, vals.data(), s);
+    capture_graph(b, vals.data(), true);
     LFEM_HIP(hipGraphLaunch(b.exec, s));
     float best = 1e30f;
     for (int r = 0; r < 3; ++r) {
@@ -256,7 +378,7 @@ float time_batch(lfem_batch_s &b, const std::vector<double *> &vals, hipStream_t
 void rebuild_all(lfem_batch_s &b, int cap, hipStream_t s)
 {
     for (int i = 0; i < b.n; ++i)
-        if (b.meshes[i]->T > 0) build_schedule(*b.meshes[i], *b.pats[i], std::max(cap, b.pats[i]->max_row), kBlockMaxRows, s);
+        if (b.fast[i] && b.meshes[i]->T > 0) build_schedule(*b.meshes[i], *b.pats[i], std::max(cap, b.pats[i]->max_row), kBlockMaxRows, s);
 }
 
 void autotune_batch(lfem_batch_s &b, hipStream_t s)
@@ -266,7 +388,7 @@ void autotune_batch(lfem_batch_s &b, hipStream_t s)
     std::vector<double *> vals(static_cast<size_t>(b.n) * b.nmat, nullptr);
     std::vector<double *> owned;
     for (int i = 0; i < b.n; ++i)
-        for (int j = 0; j < b.nmat; ++j) {
+        for (int j = 0; j < b.nmat && b.fast[i]; ++j) {
             double *v = nullptr;
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&v), std::max<int64_t>(b.pats[i]->nnz, 1) * 8));
             owned.push_back(v);
@@ -279,9 +401,9 @@ void autotune_batch(lfem_batch_s &b, hipStream_t s)
         for (int cap : caps) {
             rebuild_all(b, cap, s);
             bool ok = true;
-            for (int i = 0; i < b.n; ++i) ok = ok && batch_eligible(*b.meshes[i], *b.pats[i]);
+            for (int i = 0; i < b.n; ++i) ok = ok && (!b.fast[i] || batch_eligible(*b.meshes[i], *b.pats[i]));
             if (!ok) continue;
-            prepare(b, s);
+            prepare(b);
             const float t = time_batch(b, vals, s);
             if (verbose) std::fprintf(stderr, "[lfem tune] batch cap %d: %.1f us\n", cap, t * 1e3);
             if (t < best) {
@@ -304,28 +426,37 @@ void autotune_batch(lfem_batch_s &b, hipStream_t s)
 void batch_destroy(lfem_batch_t b);
 
 lfem_status batch_create(int n, Mesh *const *meshes, Pattern *const *pats, unsigned what,
-                         int autotune, hipStream_t s, lfem_batch_t *out)
+                         const double *const *coef_a, const double *const *coef_c, int autotune,
+                         hipStream_t s, lfem_batch_t *out)
 {
-    LFEM_REQUIRE(what == LFEM_M || what == LFEM_A || what == (LFEM_M | LFEM_A), LFEM_EINVAL,
-                 "batched assembly supports LFEM_M, LFEM_A or both");
+    LFEM_REQUIRE(what != 0 && (what & ~(LFEM_M | LFEM_A | LFEM_MC)) == 0, LFEM_EINVAL,
+                 "what must be a non-empty combination of LFEM_M, LFEM_A, LFEM_MC");
     auto *b = new lfem_batch_s();
     try {
         b->n = n;
         b->what = what;
-        b->nmat = (what & LFEM_M ? 1 : 0) + (what & LFEM_A ? 1 : 0);
+        b->nmat = (what & LFEM_M ? 1 : 0) + (what & LFEM_A ? 1 : 0) + (what & LFEM_MC ? 1 : 0);
         b->meshes.assign(meshes, meshes + n);
         b->pats.assign(pats, pats + n);
-        for (int i = 0; i < n; ++i)
-            LFEM_REQUIRE(batch_eligible(*meshes[i], *pats[i]), LFEM_EUNSUPPORTED,
-                         "batched assembly covers curves, surfaces and planar meshes under the "
-                         "default rules, whose many-contribution entries are diagonal");
+        b->coef_a.assign(n, nullptr);
+        b->coef_c.assign(n, nullptr);
+        b->fast.assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            if (coef_a) b->coef_a[i] = coef_a[i];
+            if (coef_c) b->coef_c[i] = coef_c[i];
+            LFEM_REQUIRE(!(what & LFEM_MC) || b->coef_c[i] || pats[i]->nnz == 0, LFEM_EINVAL,
+                         "the weighted mass needs a nodal coefficient for every mesh");
+            b->fast[i] = batch_eligible(*meshes[i], *pats[i]) && !b->coef_a[i] && !(what & LFEM_MC);
+            b->nfast += b->fast[i];
+        }
         LFEM_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         LFEM_HIP(hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming));
         LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&b->counter), sizeof(int)));
         LFEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&b->pinned), sizeof(BlockArgs) * n,
                                hipHostMallocDefault));
-        if (autotune) autotune_batch(*b, s);
-        prepare(*b, s);
+        if (autotune && b->nfast > 0) autotune_batch(*b, s);
+        prepare(*b);
+        warm_members(*b, s);
     } catch (...) {
         batch_destroy(b);
         throw;
@@ -340,21 +471,30 @@ void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s)
         for (int j = 0; j < b->nmat; ++j)
             LFEM_REQUIRE(vals[static_cast<size_t>(i) * b->nmat + j] || b->pats[i]->nnz == 0,
                          LFEM_EINVAL, "null output in batch");
-    // a pattern whose block schedule was rebuilt since the graph was captured
+    // a pattern whose block schedule was rebuilt since the batch was set up
     // (lfem_pattern_autotune, another batch's tuning) has freed the schedule the
-    // descriptors point at: wait for earlier replays, then rebuild the work
-    // list, descriptors and graph from the current schedules
+    // graph and descriptors point at: wait for earlier replays, then rebuild
+    // the work list, descriptors and graph from the current schedules
     bool stale = false;
     for (int i = 0; i < b->n; ++i) stale = stale || b->pats[i]->sched_gen != b->gens[i];
     if (stale) {
         LFEM_HIP(hipStreamSynchronize(s));
+        // a member rescheduled into a form the persistent kernel does not run
+        // (staged only) gets a launch of its own
         for (int i = 0; i < b->n; ++i)
-            LFEM_REQUIRE(batch_eligible(*b->meshes[i], *b->pats[i]), LFEM_EUNSUPPORTED,
-                         "a pattern of the batch was rescheduled into a form the batch kernel "
-                         "does not run (colour mode or staged only)");
-        prepare(*b, s);
+            if (b->fast[i] && !batch_eligible(*b->meshes[i], *b->pats[i])) {
+                b->fast[i] = 0;
+                --b->nfast;
+            }
+        prepare(*b);
+        warm_members(*b, s);
     }
     upload_descriptors(*b, vals, s);
+    if (members_moved(*b, vals)) {
+        // earlier replays of the graph being replaced may still run
+        LFEM_HIP(hipStreamSynchronize(s));
+        capture_graph(*b, vals, false);
+    }
     LFEM_HIP(hipGraphLaunch(b->exec, s));
 }
 

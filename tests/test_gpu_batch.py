@@ -1,6 +1,7 @@
-"""Batched multi-mesh assembly (one persistent launch replayed from a HIP graph)
-against per-mesh launches (bitwise: same schedule, same summation order) and
-against the oracle."""
+"""Batched multi-mesh assembly (one HIP graph replay: the persistent kernel for
+its family of meshes, a launch of its own for every other member) against
+per-mesh launches (bitwise: same schedule, same summation order) and against
+the oracle."""
 
 import numpy as np
 import pytest
@@ -8,7 +9,7 @@ import torch
 
 import meshgen
 import oracle
-from gpu_util import assert_csr_close
+from gpu_util import assert_csr_close, order_mesh
 from meshgen import meshes as mg
 
 pytestmark = pytest.mark.gpu
@@ -114,14 +115,14 @@ def test_batch_edge_cases(lf):
     torch.cuda.synchronize()
     assert torch.equal(v, ref)
     lf.lfem_batch_destroy(b)
-    # tetrahedra are outside the batch family
-    tet = meshgen.small_mesh("bulk", 3, 2, size=2)
-    dt = lf.DeviceMesh.from_dict(tet)
-    dt.build_pattern()
+    # argument errors
     with pytest.raises(lf.LfemError) as ei:
-        lf.lfem_batch_create([dt.handle], [dt.pattern], lf.LFEM_M)
-    assert ei.value.status == 6
-    for x in (d, de, dt):
+        lf.lfem_batch_create([d.handle], [d.pattern], 8)
+    assert ei.value.status == lf.LFEM_EINVAL
+    with pytest.raises(lf.LfemError) as ei:  # the weighted mass without its weight
+        lf.lfem_batch_create([d.handle], [d.pattern], lf.LFEM_MC)
+    assert ei.value.status == lf.LFEM_EINVAL
+    for x in (d, de):
         x.close()
 
 
@@ -212,6 +213,146 @@ def test_config4_full_batch(lf):
         for j, kind in enumerate(("mass", "stiffness")):
             assert_csr_close(rp, ci, vals[2 * i + j][:dms[i].nnz].cpu().numpy(), oracle.assemble(ms[i], kind),
                              what=f"config4 mesh {i} {kind}")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+
+
+def mixed_family_meshes():
+    """Members inside and outside the persistent kernel's family: P1 curve and
+    P2 surface (inside), a P2 surface under the 16-point rule, P2 and cubic
+    tetrahedra, a quartic planar mesh and a cubic curve (outside)."""
+    out = [meshgen.small_mesh("surface", 1, 1, size=3), meshgen.small_mesh("surface", 2, 2, size=3),
+           dict(meshgen.small_mesh("surface", 2, 2, size=2), quad=16),
+           meshgen.small_mesh("bulk", 3, 2, size=2), order_mesh("bulk", 3, 3), order_mesh("bulk", 2, 4),
+           order_mesh("surface", 1, 3)]
+    rng = np.random.default_rng(7)
+    for m in out:
+        N = m["coords"].shape[1]
+        m.setdefault("coef_a", rng.uniform(0.5, 2.0, size=N))
+        m.setdefault("coef_c", rng.uniform(0.5, 2.0, size=N))
+    return out
+
+
+def check_members(lf, ms, dms, vals, keys, coefs, label):
+    nmat = len(keys)
+    for i, (m, d) in enumerate(zip(ms, dms)):
+        ca, cc = coefs[i]
+        w = sum({"M": lf.LFEM_M, "A": lf.LFEM_A, "MC": lf.LFEM_MC}[k] for k in keys)
+        single = d.assemble(w, coef_a=ca, coef_c=cc)
+        rp, ci = (x.cpu().numpy() for x in d.pattern_tensors())
+        for j, key in enumerate(keys):
+            got = vals[i * nmat + j][:d.nnz]
+            assert torch.equal(got, single[key]), (label, i, key)
+            if key == "M":
+                ref = oracle.assemble(m, "mass")
+            elif key == "MC":
+                ref = oracle.assemble(m, "mass", coef=m["coef_c"])
+            else:
+                ref = oracle.assemble(m, "stiffness", coef=m["coef_a"] if ca is not None else None)
+            assert_csr_close(rp, ci, got.cpu().numpy(), ref, what=f"{label} mesh {i} {key}")
+
+
+@pytest.mark.parametrize("autotune", [0, 1])
+def test_batch_mixed_members(lf, autotune):
+    """Plain M and A over members in and outside the persistent kernel's
+    family, one graph replay; each output bitwise equal to lfem_assemble with
+    the tuned scatter and within tolerance of the oracle; replays with new
+    outputs (graph captured again) equal the first."""
+    ms = mixed_family_meshes()
+    print("mixed batch:", [(m["domain"], m["dim"], m["order"], m.get("quad")) for m in ms], flush=True)
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w, autotune=autotune)
+    check_members(lf, ms, dms, vals, ("M", "A"), [(None, None)] * len(ms), "mixed")
+    ref = [v.clone() for v in vals]
+    vals2 = [torch.full_like(v, float("nan")) for v in vals]
+    for _ in range(2):
+        lf.lfem_assemble_batch(b, vals2)
+    lf.lfem_assemble_batch(b, vals)
+    torch.cuda.synchronize()
+    for r, v1, v2 in zip(ref, vals, vals2):
+        assert torch.equal(r, v1) and torch.equal(r, v2)
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+
+
+def test_batch_coefficients_and_weighted_mass(lf):
+    """M, A_a and M_c for every member (all outside the persistent kernel,
+    which runs plain M and A); coefficient values changed between replays are
+    read by the next replay."""
+    ms = mixed_family_meshes()
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    ca = [torch.as_tensor(m["coef_a"], device="cuda") for m in ms]
+    cc = [torch.as_tensor(m["coef_c"], device="cuda") for m in ms]
+    w = lf.LFEM_M | lf.LFEM_A | lf.LFEM_MC
+    b = lf.lfem_batch_create_ex([d.handle for d in dms], [d.pattern for d in dms], w, ca, cc)
+    vals = [torch.full((max(d.nnz, 1),), float("nan"), dtype=torch.float64, device="cuda")
+            for d in dms for _ in range(3)]
+    lf.lfem_assemble_batch(b, vals)
+    torch.cuda.synchronize()
+    check_members(lf, ms, dms, vals, ("M", "A", "MC"), list(zip(ca, cc)), "coefficients")
+    # new coefficient values in the same tensors: the next replay reads them
+    for i, m in enumerate(ms):
+        m["coef_a"] = m["coef_a"] * 1.5 + 0.25
+        m["coef_c"] = m["coef_c"] * 0.5 + 1.0
+        ca[i].copy_(torch.as_tensor(m["coef_a"]))
+        cc[i].copy_(torch.as_tensor(m["coef_c"]))
+    lf.lfem_assemble_batch(b, vals)
+    torch.cuda.synchronize()
+    check_members(lf, ms, dms, vals, ("M", "A", "MC"), list(zip(ca, cc)), "new coefficients")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+
+
+def test_batch_partial_coefficients(lf):
+    """A_a on some members only: the members without a coefficient stay in
+    the persistent kernel (plain A), the others get their own launch."""
+    ms = mixed_family_meshes()
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    ca = [torch.as_tensor(m["coef_a"], device="cuda") if i % 2 else None for i, m in enumerate(ms)]
+    w = lf.LFEM_M | lf.LFEM_A
+    b = lf.lfem_batch_create_ex([d.handle for d in dms], [d.pattern for d in dms], w, ca, None, 1)
+    vals = [torch.full((max(d.nnz, 1),), float("nan"), dtype=torch.float64, device="cuda")
+            for d in dms for _ in range(2)]
+    lf.lfem_assemble_batch(b, vals)
+    torch.cuda.synchronize()
+    check_members(lf, ms, dms, vals, ("M", "A"), [(c, None) for c in ca], "partial coefficients")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
+
+
+def test_batch_member_state_changes(lf):
+    """Changes the graph must follow: a member outside the persistent kernel
+    moved to new coordinates, and its pattern's staging buffer reallocated by
+    a wider assembly on the same pattern between replays."""
+    ms = mixed_family_meshes()
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    b, vals = run_batch(lf, dms, lf.LFEM_M)
+    # the cubic tetrahedra (always staged): a three-matrix assembly needs a
+    # larger staging buffer than the batch's one-matrix launch
+    i = 4
+    cc = torch.as_tensor(ms[i]["coef_c"], device="cuda")
+    dms[i].assemble(lf.LFEM_M | lf.LFEM_A | lf.LFEM_MC, coef_c=cc)
+    # the quartic planar mesh moved
+    j = 5
+    ms[j] = dict(ms[j], coords=ms[j]["coords"] * 1.25)
+    dms[j].set_coords(torch.as_tensor(ms[j]["coords"], device="cuda"))
+    vals2 = [torch.full_like(v, float("nan")) for v in vals]
+    lf.lfem_assemble_batch(b, vals2)
+    torch.cuda.synchronize()
+    check_members(lf, ms, dms, vals2, ("M",), [(None, None)] * len(ms), "state changes")
     lf.lfem_batch_destroy(b)
     for d in dms:
         d.close()

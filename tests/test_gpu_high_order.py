@@ -17,8 +17,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import grad_abs_scale
-from gpu_util import assert_csr_close
+from gpu_util import assert_csr_close, grad_abs_scale, order_mesh
 from meshgen import meshes as mg
 
 pytestmark = pytest.mark.gpu
@@ -38,53 +37,6 @@ def lf():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def order_mesh(domain, d, p, seed=0):
-    """A small curved mesh of order p with random nodal coefficients."""
-    rng = np.random.default_rng(100 + 10 * d + p + seed)
-    if domain == "surface" and d == 1:
-        V, F = mg.circle(11)
-        V, F = mg.p1_to_pp(V, F, p, mg.SEG_EDGES)
-        V = mg.normalize_rows(V) * (1.0 + 0.05 * rng.uniform(-1, 1, size=len(V)))[:, None]
-        quad = 5 if p == 3 else 6
-    elif domain == "surface" and d == 2:
-        V, F = mg.icosphere_red(1)
-        V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
-        V = mg.normalize_rows(V) * (1.0 + 0.05 * rng.uniform(-1, 1, size=len(V)))[:, None]
-        quad = 16
-    elif domain == "bulk" and d == 3:
-        V, F, _ = mg.kuhn_cube(2, order=1)
-        V, F = mg.p1_to_pp(V, F, p, mg.TET_EDGES)
-        # every non-vertex node inside the cube moved by a twentieth of the node
-        # spacing h / p (h = 1/2; a tenth folds Kuhn quartics): curved elements
-        inter = np.all((V > 1e-12) & (V < 1 - 1e-12), axis=1)
-        amp = 0.05 / (2 * p)
-        V[inter] += rng.uniform(-amp, amp, size=(int(inter.sum()), 3))
-        quad = 35
-    else:
-        V, F = mg.square_tri(3)
-        V, F = mg.p1_to_pp(V, F, p, mg.TRI_EDGES)
-        inter = np.all((V > 1e-12) & (V < 1 - 1e-12), axis=1)
-        # a tenth of the node spacing h / p (h = 1/3): larger moves fold
-        # quartic elements (det J changing sign inside one element)
-        amp = 0.1 / (3 * p)
-        V[inter] += rng.uniform(-amp, amp, size=(int(inter.sum()), 2))
-        quad = 16
-    coords, conn = mg.to_soa(V, F)
-    if domain == "bulk":
-        # every element valid: det J of one sign at points spread over the element
-        if d == 2:
-            xi = np.array([(i / 8, j / 8) for i in range(9) for j in range(9 - i)])
-        else:
-            xi = np.array([(i / 6, j / 6, l / 6) for i in range(7) for j in range(7 - i) for l in range(7 - i - j)])
-        for e in range(conn.shape[1]):
-            x = coords[:, conn[:, e]]
-            dets = [np.linalg.det(x @ oracle.basis(d, p, pt)[1]) for pt in xi]
-            assert min(dets) > 0 or max(dets) < 0, f"folded element {e}"
-    N = coords.shape[1]
-    return dict(domain=domain, dim=d, order=p, quad=quad, coords=coords, conn=conn,
-                coef_a=rng.uniform(0.5, 2.0, size=N), coef_c=rng.uniform(0.5, 2.0, size=N))
 
 
 @pytest.mark.parametrize("t", TYPES + TET_TYPES)
@@ -147,16 +99,21 @@ def test_vectors(lf, t):
     dm.close()
 
 
-def test_rules_and_batch_limits(lf):
+def test_rules_and_batch_member(lf):
     m = order_mesh("surface", 2, 3)
     with pytest.raises(lf.LfemError) as e:
         lf.DeviceMesh.from_dict(dict(m, quad=6))  # orders 3, 4 take the high-order rules
     assert e.value.status == lf.LFEM_EUNSUPPORTED
     dm = lf.DeviceMesh.from_dict(dict(m, quad=0))  # default: the 16-point rule
     dm.build_pattern()
-    with pytest.raises(lf.LfemError) as e:
-        lf.lfem_batch_create([dm.handle], [dm.pattern], lf.LFEM_M | lf.LFEM_A, 0)
-    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    # a batch of one cubic mesh: its own launch inside the batch's graph
+    b = lf.lfem_batch_create([dm.handle], [dm.pattern], lf.LFEM_M | lf.LFEM_A, 0)
+    vals = [torch.full((dm.nnz,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(2)]
+    lf.lfem_assemble_batch(b, vals)
+    single = dm.assemble(lf.LFEM_M | lf.LFEM_A)
+    torch.cuda.synchronize()
+    assert torch.equal(vals[0], single["M"]) and torch.equal(vals[1], single["A"])
+    lf.lfem_batch_destroy(b)
     out = dm.assemble(lf.LFEM_M)
     rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
     assert_csr_close(rp, ci, out["M"].cpu().numpy(), oracle.assemble(m, "mass"), what="default rule")

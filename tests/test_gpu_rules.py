@@ -112,13 +112,19 @@ def test_high_order_rule_differs_from_default(lf, t, q):
     dh.close()
 
 
-def test_batch_rejects_high_order_rule(lf):
+def test_batch_member_with_high_order_rule(lf):
+    """A high-order rule is outside the persistent kernel: the batch assembles
+    that mesh with its own launch in the graph, bitwise as a single call."""
     m = with_rule(meshgen.small_mesh("surface", 2, 2, size=2), 16)
     dm = lf.DeviceMesh.from_dict(m)
-    dm.assemble(lf.LFEM_M | lf.LFEM_A, scatter=lf.LFEM_SCATTER_BLOCKED)
-    with pytest.raises(lf.LfemError) as e:
-        lf.lfem_batch_create([dm.handle], [dm.pattern], lf.LFEM_M | lf.LFEM_A, 0)
-    assert e.value.status == lf.LFEM_EUNSUPPORTED
+    dm.build_pattern()
+    b = lf.lfem_batch_create([dm.handle], [dm.pattern], lf.LFEM_M | lf.LFEM_A, 0)
+    vals = [torch.full((dm.nnz,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(2)]
+    lf.lfem_assemble_batch(b, vals)
+    single = dm.assemble(lf.LFEM_M | lf.LFEM_A)
+    torch.cuda.synchronize()
+    assert torch.equal(vals[0], single["M"]) and torch.equal(vals[1], single["A"])
+    lf.lfem_batch_destroy(b)
     dm.close()
 
 

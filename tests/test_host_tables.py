@@ -47,13 +47,13 @@ def test_rule_and_basis_match_oracle(lf, d, p, q):
 
 def test_defaults(lf):
     want = {(1, 1): 2, (1, 2): 3, (1, 3): 5, (1, 4): 6, (2, 1): 3, (2, 2): 6, (2, 3): 16, (2, 4): 16,
-            (3, 1): 4, (3, 2): 11}
+            (3, 1): 4, (3, 2): 11, (3, 3): 35, (3, 4): 35}
     for (d, p), q in want.items():
         assert len(lf.lfem_reference_table(d, p, 0)["w"]) == q
 
 
 def test_unsupported(lf):
-    for d, p, q in ((3, 3, 0), (2, 5, 0), (2, 2, 7), (1, 1, 4)):
+    for d, p, q in ((3, 5, 0), (2, 5, 0), (2, 2, 7), (1, 1, 4)):
         with pytest.raises(lf.LfemError) as e:
             lf.lfem_reference_table(d, p, q)
         assert e.value.status == lf.LFEM_EUNSUPPORTED
