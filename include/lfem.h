@@ -85,6 +85,10 @@ typedef int lfem_status;
 #define LFEM_SCATTER_STAGED 2   /* deterministic: local matrices staged, slot-sorted segmented sum */
 #define LFEM_SCATTER_ATOMIC 3   /* FP64 atomics into zeroed values; summation order not fixed */
 
+/* flags of lfem_pattern_autotune_ex */
+#define LFEM_TUNE_ALLOW_ATOMIC 1u /* also time the atomic scatter (its summation order is not fixed) */
+#define LFEM_TUNE_NO_CACHE 2u     /* time the candidates even when the cache holds a result; refresh it */
+
 typedef struct lfem_mesh_s *lfem_mesh_t;
 typedef struct lfem_pattern_s *lfem_pattern_t;
 typedef struct lfem_batch_s *lfem_batch_t;
@@ -253,13 +257,47 @@ lfem_status lfem_kll_system(lfem_mesh_t m, lfem_pattern_t p, double tau, double 
 
 /*
  * Autotune the scatter variant and row-block size of pattern p for the
- * matrix set `what` by timing the candidates on stream (SYNCHRONISES).
- * The choice is kept in the pattern and used by LFEM_SCATTER_AUTO.
- * *variant_out (may be NULL) receives the chosen LFEM_SCATTER_* value.
- * Scratch outputs are allocated and freed inside.
+ * matrix set `what` (LFEM_M, LFEM_A or both) by timing the candidates on
+ * stream (SYNCHRONISES): the blocked scatter at block capacities 2048 to
+ * 8192 value entries (those the longest row and the LDS admit), the staged
+ * scatter, and the atomic one only with LFEM_TUNE_ALLOW_ATOMIC.  The choice
+ * is kept in the pattern and used by LFEM_SCATTER_AUTO (and by batches and
+ * the step calls).  Results are cached for the life of the process, keyed by
+ * device, element type, rule, `what`, size bucket (bit length of the element
+ * count) and the atomic flag: a later call for a mesh with the same key
+ * applies the cached choice without timing (unless LFEM_TUNE_NO_CACHE, which
+ * times and refreshes the entry, or the cached capacity does not fit the new
+ * pattern's longest row).  Tuning rebuilds the block schedule, which any
+ * batch holding the pattern notices at its next run.  *variant_out and
+ * *block_cap_out (either may be NULL) receive the choice (the capacity 0
+ * unless blocked).  Scratch outputs are allocated and freed inside.
  */
+lfem_status lfem_pattern_autotune_ex(lfem_mesh_t m, lfem_pattern_t p, unsigned what, unsigned flags,
+                                     void *stream, int *variant_out, int *block_cap_out);
+
+/* lfem_pattern_autotune_ex with flags 0 (deterministic candidates, cache on). */
 lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what, void *stream,
                                   int *variant_out);
+
+/* Empty the autotuner's result cache (the patterns keep their choices). */
+void lfem_tune_cache_clear(void);
+
+/*
+ * Manual schedule knob: make `variant` (LFEM_SCATTER_BLOCKED, _STAGED or
+ * _ATOMIC) the pattern's LFEM_SCATTER_AUTO choice.  For the blocked scatter,
+ * block_cap is the number of CSR value entries one workgroup holds in LDS per
+ * matrix (0: the default, 4992 clamped to the longest row); the rows of a
+ * block, and with them the elements one workgroup assembles, follow from it
+ * (lfem_pattern_info reports max_block_rows and max_block_elems).  block_cap
+ * must lie in [longest row, 20480] and hold one row with its side slots
+ * (else LFEM_EINVAL); a capacity whose LDS
+ * for the requested matrices exceeds 160 KiB fails at assembly with
+ * LFEM_EUNSUPPORTED.  Orders 3 and 4 have no block schedule
+ * (LFEM_EUNSUPPORTED for a blocked request; their blocked requests run
+ * staged anyway).  Rebuilding the schedule is asynchronous on stream apart
+ * from its host part (the block partition is built on the host).
+ */
+lfem_status lfem_pattern_schedule(lfem_mesh_t m, lfem_pattern_t p, int variant, int block_cap, void *stream);
 
 /*
  * Batched assembly (section 6.1's many-meshes workload): n meshes of uneven
@@ -403,6 +441,22 @@ const char *lfem_last_error(void);
 
 /* Library version string. */
 const char *lfem_version(void);
+
+/*
+ * Debug mode (a development aid; off unless the environment
+ * variable LFEM_DEBUG=1 is set when the library loads, or this call turns it
+ * on).  While on, every call that reads a mesh's connectivity (the assembly,
+ * step, load, mean-curvature-flow, energy and shape-gradient calls, autotuning
+ * and batches at creation and at every run) first runs a bounds check on the
+ * GPU: each node id in [0, N), and, for calls that assemble into a pattern,
+ * the slot of every local pair (a, b) inside row conn[a] holding column
+ * conn[b] (catches a connectivity edited after the pattern was built).  The
+ * first failing element is reported as LFEM_EINVAL, naming the element and
+ * the reason (lfem_last_error), and nothing is launched.  The check
+ * SYNCHRONISES the stream and must not be captured into a graph; checks from
+ * several threads are serialised.  Returns the previous setting.
+ */
+int lfem_set_debug(int on);
 
 /* Release a handle and its device buffers.  Each destroy call first waits
  * for all work on the device (hipDeviceSynchronize), since work on any stream

@@ -37,11 +37,30 @@ OK, EINVAL, ENOMEM, EDEGENERATE = 0, 1, 2, 3
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O3 for the baseline x86-64 target, so no
     fused multiply-adds and no reassociation; no vendor libraries), plus the
-    long-double build used as a finite-difference reference."""
+    long-double build used as a finite-difference reference and the
+    sanitizer build of its driver."""
     for path, extra in ((_LIB, []), (_LIB_LD, ["-DORACLE_LONG_DOUBLE"])):
         if force or not os.path.exists(path):
             _compile(path, extra)
+    if force or not os.path.exists(_SAN_EXE):
+        build_sanitized()
     return _LIB
+
+
+_DRIVER = os.path.join(_HERE, "sanitize_driver.c")
+_SAN_EXE = os.path.join(_HERE, "oracle_sanitized")
+
+
+def build_sanitized() -> str:
+    """The oracle and its stand-alone driver (sanitize_driver.c) compiled with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host code, gcc), every
+    finding fatal; returns the executable's path."""
+    tmp = _SAN_EXE + ".tmp"
+    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-fno-omit-frame-pointer",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-o", tmp, _DRIVER, _SRC, "-lm"], check=True)
+    os.replace(tmp, _SAN_EXE)
+    return _SAN_EXE
 
 
 def _compile(path, extra):

@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import (LFEM_A, LFEM_BULK, LFEM_EDEGENERATE, LFEM_EHIP, LFEM_EINVAL, LFEM_ENOMEM,
                    LFEM_ERANGE, LFEM_EUNSUPPORTED, LFEM_M, LFEM_MC, LFEM_OK, LFEM_SCATTER_ATOMIC,
-                   LFEM_SCATTER_AUTO, LFEM_SCATTER_BLOCKED, LFEM_SCATTER_STAGED, LFEM_SURFACE, LfemError)
+                   LFEM_SCATTER_AUTO, LFEM_SCATTER_BLOCKED, LFEM_SCATTER_STAGED, LFEM_SURFACE,
+                   LFEM_TUNE_ALLOW_ATOMIC, LFEM_TUNE_NO_CACHE, LfemError)
 
 _L = _lib.load()
 
@@ -25,11 +26,12 @@ __all__ = [
     "LFEM_A", "LFEM_BULK", "LFEM_M", "LFEM_MC", "LFEM_SCATTER_ATOMIC", "LFEM_SCATTER_AUTO",
     "LFEM_OK", "LFEM_EINVAL", "LFEM_ENOMEM", "LFEM_EHIP", "LFEM_ERANGE", "LFEM_EDEGENERATE",
     "LFEM_EUNSUPPORTED",
-    "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LfemError",
+    "LFEM_SCATTER_BLOCKED", "LFEM_SCATTER_STAGED", "LFEM_SURFACE", "LFEM_TUNE_ALLOW_ATOMIC",
+    "LFEM_TUNE_NO_CACHE", "LfemError",
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
-    "lfem_pattern_autotune", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_pattern_autotune", "lfem_pattern_autotune_ex", "lfem_tune_cache_clear", "lfem_pattern_schedule", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
+    "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version", "lfem_set_debug",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
     "library_path",
 ]
@@ -151,6 +153,29 @@ def lfem_pattern_autotune(mesh, pattern, what: int, stream=None) -> int:
     _lib.check(_L.lfem_pattern_autotune(mesh, pattern, int(what), _stream(stream), C.byref(v)),
                "lfem_pattern_autotune")
     return v.value
+
+
+def lfem_set_debug(on: bool) -> bool:
+    """Turn the library's debug bounds checks on or off; returns the previous
+    setting."""
+    return bool(_L.lfem_set_debug(1 if on else 0))
+
+
+def lfem_pattern_autotune_ex(mesh, pattern, what: int, flags: int = 0, stream=None):
+    """Returns (variant, block_cap)."""
+    v, cap = C.c_int(), C.c_int()
+    _lib.check(_L.lfem_pattern_autotune_ex(mesh, pattern, int(what), int(flags), _stream(stream), C.byref(v),
+                                           C.byref(cap)), "lfem_pattern_autotune_ex")
+    return v.value, cap.value
+
+
+def lfem_tune_cache_clear():
+    _L.lfem_tune_cache_clear()
+
+
+def lfem_pattern_schedule(mesh, pattern, variant: int, block_cap: int = 0, stream=None):
+    _lib.check(_L.lfem_pattern_schedule(mesh, pattern, int(variant), int(block_cap), _stream(stream)),
+               "lfem_pattern_schedule")
 
 
 def lfem_batch_create(meshes, patterns, what: int, autotune: int = 0, stream=None):

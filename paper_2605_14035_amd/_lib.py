@@ -30,6 +30,8 @@ LFEM_SCATTER_AUTO = 0
 LFEM_SCATTER_BLOCKED = 1
 LFEM_SCATTER_STAGED = 2
 LFEM_SCATTER_ATOMIC = 3
+LFEM_TUNE_ALLOW_ATOMIC = 1
+LFEM_TUNE_NO_CACHE = 2
 
 STATUS_NAMES = {0: "LFEM_OK", 1: "LFEM_EINVAL", 2: "LFEM_ENOMEM", 3: "LFEM_EHIP",
                 4: "LFEM_ERANGE", 5: "LFEM_EDEGENERATE", 6: "LFEM_EUNSUPPORTED"}
@@ -39,8 +41,8 @@ EXPORTS = [
     "lfem_mesh_create", "lfem_mesh_set_coords", "lfem_pattern_build", "lfem_pattern_get",
     "lfem_pattern_info",
     "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
-    "lfem_pattern_autotune", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
-    "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version",
+    "lfem_pattern_autotune", "lfem_pattern_autotune_ex", "lfem_tune_cache_clear", "lfem_pattern_schedule", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
+    "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version", "lfem_set_debug",
     "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy",
 ]
 
@@ -82,6 +84,10 @@ def load():
     L.lfem_assemble_stiffness.argtypes = [vp, vp, vp, vp, vp]
     L.lfem_assemble_weighted.argtypes = [vp, vp, vp, vp, vp]
     L.lfem_pattern_autotune.argtypes = [vp, vp, cu, vp, C.POINTER(ci)]
+    L.lfem_pattern_autotune_ex.argtypes = [vp, vp, cu, cu, vp, C.POINTER(ci), C.POINTER(ci)]
+    L.lfem_tune_cache_clear.argtypes = []
+    L.lfem_tune_cache_clear.restype = None
+    L.lfem_pattern_schedule.argtypes = [vp, vp, ci, ci, vp]
     L.lfem_batch_create.argtypes = [ci, vpp, vpp, cu, ci, vp, vpp]
     L.lfem_batch_create_ex.argtypes = [ci, vpp, vpp, cu, vpp, vpp, ci, vp, vpp]
     L.lfem_assemble_batch.argtypes = [vp, vpp, vp]
@@ -99,6 +105,7 @@ def load():
     L.lfem_last_error.argtypes = []
     L.lfem_last_error.restype = C.c_char_p
     L.lfem_version.argtypes = []
+    L.lfem_set_debug.argtypes = [ci]
     L.lfem_version.restype = C.c_char_p
     for name in ("lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy"):
         getattr(L, name).argtypes = [vp]
@@ -106,7 +113,7 @@ def load():
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("lfem_last_error", "lfem_version", "lfem_mesh_destroy",
-                        "lfem_pattern_destroy", "lfem_batch_destroy"):
+                        "lfem_pattern_destroy", "lfem_batch_destroy", "lfem_tune_cache_clear"):
             fn.restype = ci
     _lib = L
     return L

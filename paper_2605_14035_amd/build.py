@@ -13,7 +13,8 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblfem.so")
 SOURCES = ["api.cpp", "ref_tables.cpp", "tune.cpp", "symbolic.hip", "numeric.hip", "numeric_curve.hip",
-           "numeric_surface.hip", "numeric_planar.hip", "numeric_tet.hip", "adjoint.hip", "steps.hip", "batch.hip"]
+           "numeric_surface.hip", "numeric_planar.hip", "numeric_tet.hip", "adjoint.hip", "steps.hip", "batch.hip",
+           "debug.hip"]
 ARCH = os.environ.get("LFEM_ARCH", "gfx950")
 # -ffp-contract=off: no implicit fused multiply-adds; the kernels write every
 # fma they want, so one source gives the same bits wherever it is inlined

@@ -19,6 +19,8 @@ const char *last_error() { return g_last_error.c_str(); }
 
 // rows per block of the blocked scatter's default schedule
 constexpr int kMaxRows = kBlockMaxRows;
+// largest block capacity: one matrix region filling a compute unit's LDS
+constexpr int kMaxBlockCap = 160 * 1024 / 8;
 
 }  // namespace lfem
 
@@ -34,8 +36,10 @@ lfem_status batch_create(int n, Mesh *const *meshes, Pattern *const *pats, unsig
                          hipStream_t s, lfem_batch_t *out);
 void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s);
 void batch_destroy(lfem_batch_t b);
+void batch_debug_check(lfem_batch_t b, hipStream_t s);
 // tune.cpp
-int autotune_pattern(Mesh &m, Pattern &p, unsigned what, hipStream_t s);
+int autotune_pattern(Mesh &m, Pattern &p, unsigned what, unsigned flags, hipStream_t s);
+void tune_cache_clear();
 }  // namespace lfem
 
 namespace {
@@ -109,6 +113,8 @@ void check_numeric_args(const Mesh *m, const Pattern *p, unsigned what, const do
 extern "C" {
 
 const char *lfem_last_error(void) { return last_error(); }
+
+int lfem_set_debug(int on) { return set_debug(on); }
 
 const char *lfem_version(void) { return "lfem-mi355x 0.1 (gfx950, fp64)"; }
 
@@ -255,6 +261,7 @@ lfem_status lfem_assemble(lfem_mesh_t m, lfem_pattern_t p, unsigned what, const 
         o.vals_m = vals_m;
         o.vals_a = vals_a;
         o.vals_mc = vals_mc;
+        debug_check(*m, p, S(stream));
         launch_numeric(*m, *p, o, variant, S(stream));
     });
 }
@@ -269,6 +276,7 @@ lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const
         LFEM_REQUIRE(std::isfinite(tau), LFEM_EINVAL, "tau is not finite");
         int variant = p->tuned_variant;
         if (variant == LFEM_SCATTER_BLOCKED && p->sched.nb == 0 && m->T > 0) variant = LFEM_SCATTER_STAGED;
+        debug_check(*m, p, S(stream));
         launch_dziuk(*m, *p, tau, x, vals_m, vals_a, vals_s, rhs, variant, S(stream));
     });
 }
@@ -284,6 +292,7 @@ lfem_status lfem_kll_system(lfem_mesh_t m, lfem_pattern_t p, double tau, double 
         LFEM_REQUIRE(std::isfinite(tau) && std::isfinite(delta0), LFEM_EINVAL, "tau or delta0 is not finite");
         int variant = p->tuned_variant;
         if (variant == LFEM_SCATTER_BLOCKED && p->sched.nb == 0 && m->T > 0) variant = LFEM_SCATTER_STAGED;
+        debug_check(*m, p, S(stream));
         launch_kll_system(*m, *p, tau, delta0, nu, H, hist, vals_m, vals_a, vals_s, f, rhs, variant, S(stream));
     });
 }
@@ -322,15 +331,43 @@ lfem_status lfem_assemble_weighted(lfem_mesh_t m, lfem_pattern_t p, const double
                          stream);
 }
 
-lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what, void *stream,
-                                  int *variant_out)
+lfem_status lfem_pattern_autotune_ex(lfem_mesh_t m, lfem_pattern_t p, unsigned what, unsigned flags,
+                                     void *stream, int *variant_out, int *block_cap_out)
 {
     return guarded([&] {
         LFEM_REQUIRE(m && p && p->mesh == m, LFEM_EINVAL, "bad mesh/pattern");
         LFEM_REQUIRE(what != 0 && (what & ~(LFEM_M | LFEM_A)) == 0, LFEM_EINVAL,
                      "autotune supports LFEM_M | LFEM_A");
-        const int v = autotune_pattern(*m, *p, what, S(stream));
+        LFEM_REQUIRE((flags & ~(LFEM_TUNE_ALLOW_ATOMIC | LFEM_TUNE_NO_CACHE)) == 0, LFEM_EINVAL,
+                     "unknown autotune flag");
+        debug_check(*m, p, S(stream));
+        const int v = autotune_pattern(*m, *p, what, flags, S(stream));
         if (variant_out) *variant_out = v;
+        if (block_cap_out) *block_cap_out = v == LFEM_SCATTER_BLOCKED ? p->sched.cap : 0;
+    });
+}
+
+lfem_status lfem_pattern_autotune(lfem_mesh_t m, lfem_pattern_t p, unsigned what, void *stream,
+                                  int *variant_out)
+{
+    return lfem_pattern_autotune_ex(m, p, what, 0, stream, variant_out, nullptr);
+}
+
+void lfem_tune_cache_clear(void) { tune_cache_clear(); }
+
+lfem_status lfem_pattern_schedule(lfem_mesh_t m, lfem_pattern_t p, int variant, int block_cap, void *stream)
+{
+    return guarded([&] {
+        LFEM_REQUIRE(m && p && p->mesh == m, LFEM_EINVAL, "bad mesh/pattern");
+        LFEM_REQUIRE(variant >= LFEM_SCATTER_BLOCKED && variant <= LFEM_SCATTER_ATOMIC, LFEM_EINVAL,
+                     "unknown scatter variant");
+        if (variant == LFEM_SCATTER_BLOCKED && m->T > 0) {
+            LFEM_REQUIRE(block_cap == 0 || (block_cap >= p->max_row && block_cap <= kMaxBlockCap), LFEM_EINVAL,
+                         "block capacity outside [longest row, LDS limit]");
+            build_schedule(*m, *p, block_cap == 0 ? default_block_cap(p->max_row) : block_cap, kMaxRows,
+                           S(stream));
+        }
+        p->tuned_variant = variant;
     });
 }
 
@@ -351,6 +388,7 @@ lfem_status lfem_batch_create_ex(int n, const lfem_mesh_t *meshes, const lfem_pa
             ms[i] = meshes[i];
             ps[i] = pats[i];
         }
+        for (int i = 0; i < n; ++i) debug_check(*ms[i], ps[i], S(stream));
         st = batch_create(n, ms.data(), ps.data(), what, coef_a, coef_c, autotune, S(stream), out);
     });
     return g != LFEM_OK ? g : st;
@@ -366,6 +404,7 @@ lfem_status lfem_assemble_batch(lfem_batch_t b, double *const *vals, void *strea
 {
     return guarded([&] {
         LFEM_REQUIRE(b && vals, LFEM_EINVAL, "null batch or vals");
+        batch_debug_check(b, S(stream));
         batch_run(b, vals, S(stream));
     });
 }
@@ -376,6 +415,7 @@ lfem_status lfem_shape_grad(lfem_mesh_t m, const double *u, const double *v, dou
 {
     return guarded([&] {
         LFEM_REQUIRE(m && grad, LFEM_EINVAL, "null mesh or grad");
+        debug_check(*m, nullptr, S(stream));
         launch_shape_grad(*m, u, v, alpha, w, z, beta, grad, S(stream));
     });
 }
@@ -386,6 +426,7 @@ lfem_status lfem_shape_grad_noalloc(lfem_mesh_t m, const double *u, const double
 {
     return guarded([&] {
         LFEM_REQUIRE(m && grad, LFEM_EINVAL, "null mesh or grad");
+        debug_check(*m, nullptr, S(stream));
         launch_shape_grad_noalloc(*m, u, v, alpha, w, z, beta, grad, S(stream));
     });
 }
@@ -396,6 +437,7 @@ lfem_status lfem_energy(lfem_mesh_t m, const double *u, const double *v, double 
 {
     return guarded([&] {
         LFEM_REQUIRE(m && J_out, LFEM_EINVAL, "null mesh or J_out");
+        debug_check(*m, nullptr, S(stream));
         launch_energy(*m, u, v, alpha, w, z, beta, J_out, S(stream));
     });
 }
@@ -404,6 +446,7 @@ lfem_status lfem_assemble_load(lfem_mesh_t m, const double *coef_f, double *b, v
 {
     return guarded([&] {
         LFEM_REQUIRE(m && (b || m->N == 0), LFEM_EINVAL, "null mesh or b");
+        debug_check(*m, nullptr, S(stream));
         launch_load(*m, coef_f, b, S(stream));
     });
 }
@@ -412,6 +455,7 @@ lfem_status lfem_assemble_kll(lfem_mesh_t m, const double *nu, const double *H, 
 {
     return guarded([&] {
         LFEM_REQUIRE(m && ((nu && f) || m->N == 0), LFEM_EINVAL, "null mesh, nu or f");
+        debug_check(*m, nullptr, S(stream));
         launch_kll(*m, nu, H, f, S(stream));
     });
 }

@@ -498,6 +498,11 @@ void batch_run(lfem_batch_t b, double *const *vals, hipStream_t s)
     LFEM_HIP(hipGraphLaunch(b->exec, s));
 }
 
+void batch_debug_check(lfem_batch_t b, hipStream_t s)
+{
+    for (int i = 0; i < b->n; ++i) debug_check(*b->meshes[i], b->pats[i], s);
+}
+
 void batch_destroy(lfem_batch_t b)
 {
     if (!b) return;

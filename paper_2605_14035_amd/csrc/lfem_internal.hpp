@@ -224,6 +224,10 @@ struct NumericOut {
     double *vals_m = nullptr, *vals_a = nullptr, *vals_mc = nullptr;
 };
 void launch_numeric(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
+// debug mode (debug.hip): validate the connectivity (and, with a pattern,
+// its slot maps) before a launch; throws LFEM_EINVAL, synchronises s
+void debug_check(const Mesh &m, const Pattern *p, hipStream_t s);
+int set_debug(int on);
 // per element family (numeric_<family>.hip)
 void numeric_curve(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);
 void numeric_surface(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStream_t s);

@@ -37,6 +37,16 @@ def test_version_string_without_gpu():
     assert lf.lfem_last_error() == ""
 
 
+def test_host_only_calls_without_gpu():
+    """The calls that touch no device: the tuning cache reset and the debug
+    switch (its round trip returns the previous setting)."""
+    import paper_2605_14035_amd as lf
+    lf.lfem_tune_cache_clear()
+    prev = lf.lfem_set_debug(True)
+    assert lf.lfem_set_debug(False) is True
+    lf.lfem_set_debug(prev)
+
+
 def test_no_oracle_in_product_path():
     """The package never imports the oracle (they share no code)."""
     pkg = os.path.join(ROOT, "paper_2605_14035_amd")
