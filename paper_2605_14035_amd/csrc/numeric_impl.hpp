@@ -198,55 +198,78 @@ __global__ __launch_bounds__(256, 2) void k_stage2(const BlockArgs g, int64_t T,
 }
 
 // Orders 3 and 4 on tetrahedra: 20 and 35 nodes, 210 and 630 local pairs,
-// more than one thread's registers hold.  One wave per element: lanes
+// more than one thread's registers hold.  One wave per element, four waves
+// (four elements) per workgroup sharing the reference table in LDS.  Lanes
 // q < Q evaluate the geometry of point q (Jacobian from the tabulated
-// reference gradients, measure, inverse metric) into LDS, then each lane
-// takes the pairs p = lane, lane + 64, ... and forms their values
-//   M_ab = sum_q f_q phi_a phi_b,  A_ab = sum_q g_a^T K'_q g_b,
-// f_q = w_q mu_q c_h(xi_q), K'_q = w_q mu_q a_h(xi_q) K_q, from the point data
-// and the reference values (also in LDS).  The values are staged element by
-// element for the staged reduction, or with ATOMIC added to the CSR values.
+// reference gradients, measure, inverse metric) into LDS; then the local
+// matrices are two dense contractions per element on the matrix cores
+// (FP64 MFMA, 16 x 16 output tiles, 4 inner terms per instruction):
+//   A_ab = sum_{(q,m)} H_{(q,m),a} G_{(q,m),b},  H_{(q,m),a} = (K'_q g_a(xi_q))_m,
+//          G_{(q,m),b} = (g_b(xi_q))_m,
+//   M_ab = sum_q (f_q phi_a(xi_q)) phi_b(xi_q),
+// f_q = w_q mu_q c_h(xi_q), K'_q = w_q mu_q a_h(xi_q) K_q, g the reference
+// gradients.  Only the tiles on and above the diagonal are formed (the
+// matrices are symmetric); the values of the pairs a <= b are staged element
+// by element for the staged reduction, or with ATOMIC added to the CSR values.
+typedef double lfem_v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kWaveElems = 4;  // elements (waves) per workgroup
+
 template <class E, int Q, int NM, bool HA, bool ATOMIC>
-__global__ __launch_bounds__(64) void k_wave(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                             double *__restrict__ stage, const int32_t *__restrict__ row_ptr,
-                                             const uint16_t *__restrict__ off16)
+__global__ __launch_bounds__(64 * kWaveElems) void k_wave(const BlockArgs g, int64_t T,
+                                                          const int32_t *__restrict__ conn,
+                                                          double *__restrict__ stage,
+                                                          const int32_t *__restrict__ row_ptr,
+                                                          const uint16_t *__restrict__ off16)
 {
     constexpr int K = E::k, D = E::d, NA = E::n, NP = E::np, NMAT = NM + (HA ? 1 : 0);
     constexpr int RS = 1 + K + K * D;            // per point: weight, phi (K), grad phi (K x D)
     constexpr int NMS = NM > 0 ? NM : 1;
     constexpr int QS = NMS + 6;                  // per point: mass factors, then w mu a_h K (m <= l)
-    static_assert(D == 3 && Q <= 64, "one lane per point of a tetrahedral rule");
+    constexpr int NTL = (K + 15) / 16;           // 16 x 16 tiles per side
+    constexpr int SA = (D * Q + 3) / 4;          // inner steps of the stiffness contraction
+    constexpr int SM = (Q + 3) / 4;              // inner steps of the mass contraction
+    constexpr int W = kWaveElems;
+    static_assert(D == 3 && NA == 3 && Q <= 64, "one lane per point of a tetrahedral rule");
     __shared__ double ref[Q * RS];
-    __shared__ double xs[K * NA];
-    __shared__ double qd[Q * QS];
-    __shared__ int32_t nid[K];
-    __shared__ uint8_t pa[NP], pb[NP];
-    const int lane = threadIdx.x;
-    for (int i = lane; i < Q * RS; i += 64) {
+    __shared__ double xs[2][W][K * NA];  // node coordinates, double-buffered across elements
+    __shared__ double qd[W][Q * QS];
+    __shared__ int32_t nid[2][W][K];
+    static_assert(K * NA <= 128, "two coordinates per lane");
+    const int wave = static_cast<int>(threadIdx.x) >> 6, lane = static_cast<int>(threadIdx.x) & 63;
+    for (int i = threadIdx.x; i < Q * RS; i += 64 * W) {
         const int q = i / RS, j = i - q * RS;
         const int src = j == 0 ? 0 : (j <= K ? E::off_phi + (j - 1) : E::off_g + (j - 1 - K));
         ref[i] = g.tab[q * E::stride + src];
     }
-    for (int p = lane; p < NP; p += 64) {  // pair p = (a, b), a <= b, row-major upper triangle
-        int a = 0, first = 0;
-        while (first + (K - a) <= p) {
-            first += K - a;
-            ++a;
-        }
-        pa[p] = static_cast<uint8_t>(a);
-        pb[p] = static_cast<uint8_t>(a + (p - first));
-    }
     const double *cms[2] = {g.cm0, g.cm1};
-    for (int64_t e = blockIdx.x; e < T; e += gridDim.x) {
-        __syncthreads();  // the previous element's LDS data are consumed
-        if (lane < K) nid[lane] = conn[lane * T + e];
+    // the same trip count in every wave, so the barriers below are uniform
+    const int64_t per = static_cast<int64_t>(gridDim.x) * W;
+    const int64_t iters = (T + per - 1) / per;
+    const int li = lane & 15, lk = lane >> 4;  // MFMA operand row / inner index of this lane
+    // the first element's node ids and coordinates; later elements' are loaded
+    // while the previous one computes (ids during its geometry, coordinates
+    // during its contractions)
+    {
+        const int64_t e0 = static_cast<int64_t>(blockIdx.x) * W + wave;
+        if (e0 < T && lane < K) nid[0][wave][lane] = conn[lane * T + e0];
         __syncthreads();
-        for (int i = lane; i < K * NA; i += 64) {
-            const int a = i / NA, c = i - a * NA;
-            xs[i] = g.coords[c * g.N + nid[a]];
-        }
+        if (e0 < T)
+            for (int i = lane; i < K * NA; i += 64) {
+                const int a = i / NA, c = i - a * NA;
+                xs[0][wave][i] = g.coords[c * g.N + nid[0][wave][a]];
+            }
         __syncthreads();
-        if (lane < Q) {
+    }
+    for (int64_t it = 0; it < iters; ++it) {
+        const int cb = static_cast<int>(it & 1), nb = cb ^ 1;
+        const int64_t e = (it * gridDim.x + blockIdx.x) * W + wave;
+        const bool active = e < T;
+        const int64_t en = ((it + 1) * gridDim.x + blockIdx.x) * W + wave;
+        const bool nact = it + 1 < iters && en < T;
+        int32_t nid_next = 0;
+        if (nact && lane < K) nid_next = conn[lane * T + en];
+        if (active && lane < Q) {
             const double *r = ref + lane * RS;
             double J[NA][D];
 #pragma unroll
@@ -254,20 +277,20 @@ __global__ __launch_bounds__(64) void k_wave(const BlockArgs g, int64_t T, const
 #pragma unroll
                 for (int m = 0; m < D; ++m) {
                     double acc = 0.0;
-                    for (int a = 0; a < K; ++a) acc = fma(xs[a * NA + c], r[1 + K + a * D + m], acc);
+                    for (int a = 0; a < K; ++a) acc = fma(xs[cb][wave][a * NA + c], r[1 + K + a * D + m], acc);
                     J[c][m] = acc;
                 }
             double Km[D][D], mu;
             geometry<E>(J, Km, mu);
             if (!(mu > 0.0 && mu < INFINITY)) atomicAdd(g.degenerate, 1ull);
             const double wmu = r[0] * mu;
-            double *qq = qd + lane * QS;
+            double *qq = qd[wave] + lane * QS;
 #pragma unroll
             for (int s = 0; s < NM; ++s) {
                 double f = wmu;
                 if (cms[s]) {
                     double ch = 0.0;
-                    for (int a = 0; a < K; ++a) ch = fma(cms[s][nid[a]], r[1 + a], ch);
+                    for (int a = 0; a < K; ++a) ch = fma(cms[s][nid[cb][wave][a]], r[1 + a], ch);
                     f *= ch;
                 }
                 qq[s] = f;
@@ -276,7 +299,7 @@ __global__ __launch_bounds__(64) void k_wave(const BlockArgs g, int64_t T, const
                 double fa = wmu;
                 if (g.ca) {
                     double ah = 0.0;
-                    for (int a = 0; a < K; ++a) ah = fma(g.ca[nid[a]], r[1 + a], ah);
+                    for (int a = 0; a < K; ++a) ah = fma(g.ca[nid[cb][wave][a]], r[1 + a], ah);
                     fa *= ah;
                 }
                 qq[NMS + 0] = fa * Km[0][0];
@@ -287,40 +310,123 @@ __global__ __launch_bounds__(64) void k_wave(const BlockArgs g, int64_t T, const
                 qq[NMS + 5] = fa * Km[2][2];
             }
         }
-        __syncthreads();
-        for (int p = lane; p < NP; p += 64) {
-            const int a = pa[p], b = pb[p];
-            double v[NMAT];
+        if (nact && lane < K) nid[nb][wave][lane] = nid_next;
+        __syncthreads();  // point data and the next element's node ids in place
+        double cx[2] = {0.0, 0.0};
+        if (nact)
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) v[mat] = 0.0;
-            for (int q = 0; q < Q; ++q) {
-                const double *r = ref + q * RS;
-                const double *qq = qd + q * QS;
-                const double pp = r[1 + a] * r[1 + b];
-#pragma unroll
-                for (int s = 0; s < NM; ++s) v[s] = fma(qq[s], pp, v[s]);
-                if constexpr (HA) {
-                    const double *ga = r + 1 + K + a * D, *gb = r + 1 + K + b * D;
-                    const double h0 = fma(qq[NMS + 0], ga[0], fma(qq[NMS + 1], ga[1], qq[NMS + 2] * ga[2]));
-                    const double h1 = fma(qq[NMS + 1], ga[0], fma(qq[NMS + 3], ga[1], qq[NMS + 4] * ga[2]));
-                    const double h2 = fma(qq[NMS + 2], ga[0], fma(qq[NMS + 4], ga[1], qq[NMS + 5] * ga[2]));
-                    v[NM] = fma(h0, gb[0], fma(h1, gb[1], fma(h2, gb[2], v[NM])));
+            for (int u = 0; u < 2; ++u) {
+                const int i = lane + 64 * u;
+                if (i < K * NA) {
+                    const int a = i / NA, c = i - a * NA;
+                    cx[u] = g.coords[c * g.N + nid[nb][wave][a]];
                 }
             }
-            if constexpr (ATOMIC) {
-                const int32_t sab = row_ptr[nid[a]] + off16[(e * K + a) * K + b];
+        if (active) {
+            lfem_v4d accA[NTL][NTL], accM[NMS][NTL][NTL];
 #pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sab, v[mat]);
-                if (a != b) {
-                    const int32_t sba = row_ptr[nid[b]] + off16[(e * K + b) * K + a];
+            for (int R = 0; R < NTL; ++R)
 #pragma unroll
-                    for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sba, v[mat]);
+                for (int C = 0; C < NTL; ++C) {
+                    accA[R][C] = lfem_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < NMS; ++s) accM[s][R][C] = lfem_v4d{0.0, 0.0, 0.0, 0.0};
                 }
-            } else {
+            if constexpr (HA) {
+                // inner index kk = 4 st + lk = 3 q + m over (point, component)
+#pragma unroll 3
+                for (int st = 0; st < SA; ++st) {
+                    const int kk = 4 * st + lk;
+                    const bool kin = kk < D * Q;
+                    const int q = kin ? kk / D : 0, m = kin ? kk - D * (kk / D) : 0;
+                    const double *r = ref + q * RS;
+                    const double *qq = qd[wave] + q * QS + NMS;
+                    // row m of the symmetric K'_q (stored m <= l as 00 01 02 11 12 22)
+                    const double k0 = kin ? qq[m == 0 ? 0 : (m == 1 ? 1 : 2)] : 0.0;
+                    const double k1 = kin ? qq[m == 0 ? 1 : (m == 1 ? 3 : 4)] : 0.0;
+                    const double k2 = kin ? qq[m == 0 ? 2 : (m == 1 ? 4 : 5)] : 0.0;
+                    double bop[NTL];
 #pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) stage[(e * NP + p) * NMAT + mat] = v[mat];
+                    for (int C = 0; C < NTL; ++C) {
+                        const int b = C * 16 + li;
+                        bop[C] = kin && b < K ? r[1 + K + b * D + m] : 0.0;
+                    }
+#pragma unroll
+                    for (int R = 0; R < NTL; ++R) {
+                        const int a = R * 16 + li;
+                        double aop = 0.0;
+                        if (kin && a < K) {
+                            const double *ga = r + 1 + K + a * D;
+                            aop = fma(k0, ga[0], fma(k1, ga[1], k2 * ga[2]));
+                        }
+#pragma unroll
+                        for (int C = R; C < NTL; ++C)
+                            accA[R][C] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[C], accA[R][C], 0, 0, 0);
+                    }
+                }
             }
+            if constexpr (NM > 0) {
+#pragma unroll 3
+                for (int st = 0; st < SM; ++st) {
+                    const int q = 4 * st + lk;
+                    const bool qin = q < Q;
+                    const int qc = qin ? q : 0;  // padding terms read point 0 and multiply by 0
+                    const double *r = ref + qc * RS;
+                    double bop[NTL];
+#pragma unroll
+                    for (int C = 0; C < NTL; ++C) {
+                        const int b = C * 16 + li;
+                        bop[C] = qin && b < K ? r[1 + b] : 0.0;
+                    }
+#pragma unroll
+                    for (int R = 0; R < NTL; ++R) {
+                        const int a = R * 16 + li;
+                        const double pa = qin && a < K ? r[1 + a] : 0.0;
+#pragma unroll
+                        for (int s = 0; s < NM; ++s) {
+                            const double aop = pa * qd[wave][qc * QS + s];
+#pragma unroll
+                            for (int C = R; C < NTL; ++C)
+                                accM[s][R][C] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[C], accM[s][R][C], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            // tile (R, C) element r of this lane: a = 16 R + lk + 4 r, b = 16 C + li
+#pragma unroll
+            for (int R = 0; R < NTL; ++R)
+#pragma unroll
+                for (int C = R; C < NTL; ++C)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int a = R * 16 + lk + 4 * rr, b = C * 16 + li;
+                        if (a >= K || b >= K || a > b) continue;
+                        double v[NMAT];
+#pragma unroll
+                        for (int s = 0; s < NM; ++s) v[s] = accM[s][R][C][rr];
+                        if constexpr (HA) v[NM] = accA[R][C][rr];
+                        if constexpr (ATOMIC) {
+                            const int32_t sab = row_ptr[nid[cb][wave][a]] + off16[(e * K + a) * K + b];
+#pragma unroll
+                            for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sab, v[mat]);
+                            if (a != b) {
+                                const int32_t sba = row_ptr[nid[cb][wave][b]] + off16[(e * K + b) * K + a];
+#pragma unroll
+                                for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sba, v[mat]);
+                            }
+                        } else {
+                            const int p = pair_index<K>(a, b);
+#pragma unroll
+                            for (int mat = 0; mat < NMAT; ++mat) stage[(e * NP + p) * NMAT + mat] = v[mat];
+                        }
+                    }
         }
+        if (nact)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (lane + 64 * u < K * NA) xs[nb][wave][lane + 64 * u] = cx[u];
+        __syncthreads();  // the next element's coordinates in place; the point data consumed
     }
 }
 
@@ -561,12 +667,13 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         // one wave per element; staged (also for a blocked request: no block
         // schedule for orders above 2) or atomic
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
-        const unsigned grid = static_cast<unsigned>(std::min<int64_t>(m.T, 16384));
+        const unsigned grid =
+            static_cast<unsigned>(std::min<int64_t>((m.T + kWaveElems - 1) / kWaveElems, 4096));
         if (variant == LFEM_SCATTER_ATOMIC) {
             for (int mat = 0; mat < NMAT; ++mat)
                 k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
             with_rule<E>(m.Q, [&](auto qc) {
-                k_wave<E, decltype(qc)::value, NM, HA, true><<<grid, 64, 0, s>>>(g, m.T, m.conn, nullptr, p.row_ptr,
+                k_wave<E, decltype(qc)::value, NM, HA, true><<<grid, 64 * kWaveElems, 0, s>>>(g, m.T, m.conn, nullptr, p.row_ptr,
                                                                                  p.off16);
             });
             LFEM_HIP(hipGetLastError());
@@ -582,7 +689,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             p.stage_bytes = need;
         }
         with_rule<E>(m.Q, [&](auto qc) {
-            k_wave<E, decltype(qc)::value, NM, HA, false><<<grid, 64, 0, s>>>(g, m.T, m.conn, p.stage, p.row_ptr,
+            k_wave<E, decltype(qc)::value, NM, HA, false><<<grid, 64 * kWaveElems, 0, s>>>(g, m.T, m.conn, p.stage, p.row_ptr,
                                                                               p.off16);
         });
         LFEM_HIP(hipGetLastError());
