@@ -96,9 +96,7 @@ typedef struct lfem_batch_s *lfem_batch_t;
 /*
  * Create a mesh handle.  domain: LFEM_SURFACE or LFEM_BULK; dim: manifold
  * dimension d (surface: 1 or 2; bulk: 2 or 3); order: 1, 2, 3 or 4 (orders 3
- * and 4 take the high-order rules and the staged scatter; on tetrahedra the
- * load vector, the mean-curvature-flow terms, the shape gradient and the
- * energy are built for orders 1 and 2 only: LFEM_EUNSUPPORTED).  The ambient
+ * and 4 take the high-order rules and the staged scatter).  The ambient
  * dimension is n_amb = d + 1 (surface) or d (bulk), so coords has
  * n_amb * n_nodes entries and conn has k * n_elems entries, k = C(order+d, d).
  * quad_points selects the quadrature rule on the reference simplex by its
@@ -112,7 +110,7 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * The rules are those of the paper's quadrature forms (section 3.2.2) and the
  * high-order rules of its precomputations (section 5.2: Gauss of degree 10 or
  * more on segments, Dunavant of degree 8 on triangles, degree 7 on
- * tetrahedra), with the weights summing to the reference measure.  Batched assembly takes the two default rules only.
+ * tetrahedra), with the weights summing to the reference measure.
  * Orders 3 and 4 take only the high-order rules (defaults: segment 5 points
  * for order 3 and 6 for order 4; triangle 16; tetrahedron 35).
  * Uploads the reference tables and builds the node -> element incidence

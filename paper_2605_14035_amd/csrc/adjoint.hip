@@ -408,6 +408,8 @@ void dispatch(Mesh &m, bool grad, const double *u, const double *v, double alpha
     case B2P4: run_adj<ET<0, 2, 4>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B3P1: run_adj<ET<0, 3, 1>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     case B3P2: run_adj<ET<0, 3, 2>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B3P3: run_adj<ET<0, 3, 3>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
+    case B3P4: run_adj<ET<0, 3, 4>>(m, grad, u, v, alpha, w, z, beta, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
     }
 }
@@ -437,6 +439,8 @@ void dispatch_load(Mesh &m, const double *f, double *out, hipStream_t s)
     case B2P4: run_load<ET<0, 2, 4>>(m, f, out, s); break;
     case B3P1: run_load<ET<0, 3, 1>>(m, f, out, s); break;
     case B3P2: run_load<ET<0, 3, 2>>(m, f, out, s); break;
+    case B3P3: run_load<ET<0, 3, 3>>(m, f, out, s); break;
+    case B3P4: run_load<ET<0, 3, 4>>(m, f, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
     }
 }
@@ -467,6 +471,8 @@ void dispatch_kll(Mesh &m, const double *nu, const double *H, double *out, hipSt
     case B2P4: run_kll<ET<0, 2, 4>>(m, nu, H, out, s); break;
     case B3P1: run_kll<ET<0, 3, 1>>(m, nu, H, out, s); break;
     case B3P2: run_kll<ET<0, 3, 2>>(m, nu, H, out, s); break;
+    case B3P3: run_kll<ET<0, 3, 3>>(m, nu, H, out, s); break;
+    case B3P4: run_kll<ET<0, 3, 4>>(m, nu, H, out, s); break;
     default: throw Error{LFEM_EUNSUPPORTED, "element type"};
     }
 }

@@ -68,7 +68,7 @@ def test_matrices(lf, t, variant):
     dm.close()
 
 
-@pytest.mark.parametrize("t", TYPES)
+@pytest.mark.parametrize("t", TYPES + TET_TYPES)
 def test_vectors(lf, t):
     m = order_mesh(*t)
     say("case", t, "load, terms, gradient")
@@ -96,6 +96,10 @@ def test_vectors(lf, t):
     err = float((np.abs(gg - gref) / S).max())
     say(f"  shape gradient error {err:.2e} of sum|g_e|, {np.linalg.norm(gg - gref) / np.linalg.norm(gref):.2e} normwise")
     assert err <= 1e-12
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    lf.lfem_energy(dm.handle, ut, ut, 1.0, wt, wt, 0.5, J)
+    Jref = oracle.energy(m, u, u, 1.0, w, w, 0.5)
+    assert abs(J.item() - Jref) <= 1e-12 * abs(Jref)
     dm.close()
 
 
@@ -117,24 +121,6 @@ def test_rules_and_batch_member(lf):
     out = dm.assemble(lf.LFEM_M)
     rp, ci = (x.cpu().numpy() for x in dm.pattern_tensors())
     assert_csr_close(rp, ci, out["M"].cpu().numpy(), oracle.assemble(m, "mass"), what="default rule")
-    dm.close()
-
-
-@pytest.mark.parametrize("t", TET_TYPES)
-def test_tetrahedra_other_calls_unsupported(lf, t):
-    """Tetrahedra of orders 3 and 4 assemble matrices (above); the load vector,
-    the mean-curvature-flow terms and the shape gradient are not built for
-    them and say so."""
-    m = order_mesh(*t)
-    dm = lf.DeviceMesh.from_dict(m)
-    x = torch.ones(dm.N, dtype=torch.float64, device="cuda")
-    with pytest.raises(lf.LfemError) as e:
-        dm.load(x)
-    assert e.value.status == lf.LFEM_EUNSUPPORTED
-    g = torch.empty_like(dm.coords)
-    with pytest.raises(lf.LfemError) as e:
-        lf.lfem_shape_grad(dm.handle, x, x, 1.0, None, None, 0.0, g)
-    assert e.value.status == lf.LFEM_EUNSUPPORTED
     dm.close()
 
 
