@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import meshgen
+from gpu_util import order_mesh
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +47,10 @@ def calls(lf, d):
     return out
 
 
-@pytest.mark.parametrize("t", [("surface", 2, 2), ("bulk", 3, 2), ("surface", 1, 1)])
+@pytest.mark.parametrize("t", [("surface", 2, 2), ("bulk", 3, 2), ("surface", 1, 1), ("bulk", 3, 3)])
 def test_debug_checks(lf, debug, t):
-    m = meshgen.small_mesh(*t, size=3)
+    # the cubic tetrahedra take the 16-bit slot map
+    m = order_mesh(*t) if t[2] > 2 else meshgen.small_mesh(*t, size=3)
     d = lf.DeviceMesh.from_dict(m)
     d.build_pattern()
     lf.lfem_set_debug(False)
