@@ -430,6 +430,175 @@ __global__ __launch_bounds__(64 * kWaveElems) void k_wave(const BlockArgs g, int
     }
 }
 
+// Orders 3 and 4 on triangles (surfaces and planar meshes: 10 and 15 nodes,
+// one 16 x 16 matrix-core tile per element): four elements per wave, one
+// lane per (element, point) for the geometry (w mu c_h and w mu a_h K at the
+// 16-point rule), then per element the contractions
+//   A_ab = sum_{(q,m)} (K'_q g_a(xi_q))_m (g_b(xi_q))_m   (2 Q inner terms),
+//   M_ab = sum_q (f_q phi_a(xi_q)) phi_b(xi_q)              (Q inner terms),
+// on FP64 MFMA, the four elements' chains interleaved.  The values of the
+// pairs a <= b are staged element by element, or with ATOMIC added to the CSR
+// values through the byte slot map.
+template <class E, int Q, int NM, bool HA, bool ATOMIC>
+__global__ __launch_bounds__(256) void k_wave_tri(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
+                                                  double *__restrict__ stage, const int32_t *__restrict__ row_ptr,
+                                                  const uint8_t *__restrict__ off8, int kkp)
+{
+    constexpr int K = E::k, D = E::d, NA = E::n, NP = E::np, NMAT = NM + (HA ? 1 : 0);
+    constexpr int RS = 1 + K + K * D;  // per point: weight, phi (K), grad phi (K x D)
+    constexpr int NMS = NM > 0 ? NM : 1;
+    constexpr int QS = NMS + 3;        // per point: mass factors, then w mu a_h K (00 01 11)
+    constexpr int SA = (D * Q + 3) / 4, SM = (Q + 3) / 4;
+    constexpr int EW = 4;              // elements per wave
+    constexpr int W = 4;               // waves per workgroup
+    static_assert(D == 2 && K <= 16 && Q <= 16, "one tile and one lane group per element");
+    __shared__ double ref[Q * RS];
+    __shared__ double xs[W][EW][K * NA];
+    __shared__ double qd[W][EW][Q * QS];
+    __shared__ int32_t nid[W][EW][K];
+    const int wave = static_cast<int>(threadIdx.x) >> 6, lane = static_cast<int>(threadIdx.x) & 63;
+    for (int i = threadIdx.x; i < Q * RS; i += 64 * W) {
+        const int q = i / RS, j = i - q * RS;
+        const int src = j == 0 ? 0 : (j <= K ? E::off_phi + (j - 1) : E::off_g + (j - 1 - K));
+        ref[i] = g.tab[q * E::stride + src];
+    }
+    const double *cms[2] = {g.cm0, g.cm1};
+    const int64_t per = static_cast<int64_t>(gridDim.x) * W * EW;
+    const int64_t iters = (T + per - 1) / per;  // the same in every wave: uniform barriers
+    const int li = lane & 15, lk = lane >> 4;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t e0 = ((it * gridDim.x + blockIdx.x) * W + wave) * EW;  // this wave's first element
+        __syncthreads();  // reference table in place; the previous elements' data consumed
+        for (int i = lane; i < EW * K; i += 64) {
+            const int j = i / K, a = i - j * K;
+            if (e0 + j < T) nid[wave][j][a] = conn[a * T + e0 + j];
+        }
+        __syncthreads();
+        for (int i = lane; i < EW * K * NA; i += 64) {
+            const int j = i / (K * NA), r = i - j * (K * NA), a = r / NA, c = r - a * NA;
+            if (e0 + j < T) xs[wave][j][r] = g.coords[c * g.N + nid[wave][j][a]];
+        }
+        __syncthreads();
+        {
+            const int j = lane >> 4, q = lane & 15;
+            if (q < Q && e0 + j < T) {
+                const double *r = ref + q * RS;
+                double J[NA][D];
+#pragma unroll
+                for (int c = 0; c < NA; ++c)
+#pragma unroll
+                    for (int m = 0; m < D; ++m) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int a = 0; a < K; ++a) acc = fma(xs[wave][j][a * NA + c], r[1 + K + a * D + m], acc);
+                        J[c][m] = acc;
+                    }
+                double Km[D][D], mu;
+                geometry<E>(J, Km, mu);
+                if (!(mu > 0.0 && mu < INFINITY)) atomicAdd(g.degenerate, 1ull);
+                const double wmu = r[0] * mu;
+                double *qq = qd[wave][j] + q * QS;
+#pragma unroll
+                for (int s = 0; s < NM; ++s) {
+                    double f = wmu;
+                    if (cms[s]) {
+                        double ch = 0.0;
+#pragma unroll
+                        for (int a = 0; a < K; ++a) ch = fma(cms[s][nid[wave][j][a]], r[1 + a], ch);
+                        f *= ch;
+                    }
+                    qq[s] = f;
+                }
+                if constexpr (HA) {
+                    double fa = wmu;
+                    if (g.ca) {
+                        double ah = 0.0;
+#pragma unroll
+                        for (int a = 0; a < K; ++a) ah = fma(g.ca[nid[wave][j][a]], r[1 + a], ah);
+                        fa *= ah;
+                    }
+                    qq[NMS + 0] = fa * Km[0][0];
+                    qq[NMS + 1] = fa * Km[0][1];
+                    qq[NMS + 2] = fa * Km[1][1];
+                }
+            }
+        }
+        __syncthreads();
+        lfem_v4d accA[EW], accM[NMS][EW];
+#pragma unroll
+        for (int j = 0; j < EW; ++j) {
+            accA[j] = lfem_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NMS; ++s) accM[s][j] = lfem_v4d{0.0, 0.0, 0.0, 0.0};
+        }
+        if constexpr (HA) {
+            // inner index kk = 4 st + lk = 2 q + m over (point, component)
+#pragma unroll
+            for (int st = 0; st < SA; ++st) {
+                const int kk = 4 * st + lk;
+                const bool kin = kk < D * Q;
+                const int q = kin ? kk / D : 0, m = kin ? kk - D * (kk / D) : 0;
+                const double *r = ref + q * RS;
+                const double bop = kin && li < K ? r[1 + K + li * D + m] : 0.0;
+                const bool ain = kin && li < K;
+                const double ga0 = ain ? r[1 + K + li * D] : 0.0, ga1 = ain ? r[1 + K + li * D + 1] : 0.0;
+#pragma unroll
+                for (int j = 0; j < EW; ++j) {
+                    const double *qq = qd[wave][j] + q * QS + NMS;
+                    // row m of the symmetric K'_q
+                    const double k0 = qq[m == 0 ? 0 : 1], k1 = qq[m == 0 ? 1 : 2];
+                    const double aop = fma(k0, ga0, k1 * ga1);
+                    accA[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, accA[j], 0, 0, 0);
+                }
+            }
+        }
+        if constexpr (NM > 0) {
+#pragma unroll
+            for (int st = 0; st < SM; ++st) {
+                const int q = 4 * st + lk;
+                const int qc = q < Q ? q : 0;  // padding terms multiply by 0
+                const double *r = ref + qc * RS;
+                const double ph = q < Q && li < K ? r[1 + li] : 0.0;
+#pragma unroll
+                for (int j = 0; j < EW; ++j)
+#pragma unroll
+                    for (int s = 0; s < NM; ++s)
+                        accM[s][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph * qd[wave][j][qc * QS + s], ph,
+                                                                         accM[s][j], 0, 0, 0);
+            }
+        }
+        // element j, value r of this lane: a = lk + 4 r, b = li
+#pragma unroll
+        for (int j = 0; j < EW; ++j) {
+            const int64_t e = e0 + j;
+            if (e >= T) continue;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int a = lk + 4 * rr, b = li;
+                if (a >= K || b >= K || a > b) continue;
+                double v[NMAT];
+#pragma unroll
+                for (int s = 0; s < NM; ++s) v[s] = accM[s][j][rr];
+                if constexpr (HA) v[NM] = accA[j][rr];
+                if constexpr (ATOMIC) {
+                    const int32_t sab = row_ptr[nid[wave][j][a]] + off8[e * kkp + a * K + b];
+#pragma unroll
+                    for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sab, v[mat]);
+                    if (a != b) {
+                        const int32_t sba = row_ptr[nid[wave][j][b]] + off8[e * kkp + b * K + a];
+#pragma unroll
+                        for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sba, v[mat]);
+                    }
+                } else {
+                    const int p = pair_index<K>(a, b);
+#pragma unroll
+                    for (int mat = 0; mat < NMAT; ++mat) stage[(e * NP + p) * NMAT + mat] = v[mat];
+                }
+            }
+        }
+    }
+}
+
 // sum of the contributions of CSR value s, in ascending element order, up to
 // kReduceBatch loads in flight
 template <int K, int NMAT>
@@ -661,6 +830,46 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             if (p.nnz > 0) {
                 k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
             }
+        return;
+    }
+    if constexpr (E::d == 2 && E::p >= 3) {
+        // four elements per wave on the matrix cores; staged (also for a
+        // blocked request: no block schedule for orders above 2) or atomic
+        const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
+        const unsigned grid = static_cast<unsigned>(std::min<int64_t>((m.T + 15) / 16, 4096));
+        if (variant == LFEM_SCATTER_ATOMIC) {
+            for (int mat = 0; mat < NMAT; ++mat)
+                k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
+            with_rule<E>(m.Q, [&](auto qc) {
+                k_wave_tri<E, decltype(qc)::value, NM, HA, true><<<grid, 256, 0, s>>>(g, m.T, m.conn, nullptr,
+                                                                                    p.row_ptr, p.off8, p.kkp);
+            });
+            LFEM_HIP(hipGetLastError());
+            return;
+        }
+        build_staged(m, p, s);
+        const size_t need = static_cast<size_t>(NMAT) * E::np * m.T * sizeof(double);
+        if (p.stage_bytes < need) {
+            dev_free(p.stage);
+            p.stage = nullptr;
+            p.stage_bytes = 0;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
+            p.stage_bytes = need;
+        }
+        with_rule<E>(m.Q, [&](auto qc) {
+            k_wave_tri<E, decltype(qc)::value, NM, HA, false><<<grid, 256, 0, s>>>(g, m.T, m.conn, p.stage,
+                                                                                 p.row_ptr, p.off8, p.kkp);
+        });
+        LFEM_HIP(hipGetLastError());
+        k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
+                                                                   o.v[1], o.v[2]);
+        LFEM_HIP(hipGetLastError());
+        if (p.nlong > 0) {
+            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
+                                                                             p.clist, p.stage, o.v[0], o.v[1],
+                                                                             o.v[2]);
+            LFEM_HIP(hipGetLastError());
+        }
         return;
     }
     if constexpr (E::d == 3 && E::p >= 3) {
