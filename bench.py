@@ -428,8 +428,8 @@ def main():
                          "calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); multi-GPU runs are "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the assembly would shard by "
+              "node ranges without communication, but no multi-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
