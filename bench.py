@@ -121,15 +121,30 @@ def batched_vs_plain(lf, torch, meshgen, reps=5):
     vals = [torch.empty(max(d.nnz, 1), dtype=torch.float64, device="cuda") for d in dms for _ in range(2)]
     stream = torch.cuda.current_stream()
 
-    def plain():
+    # both sides with their arguments marshalled once (the per-call Python
+    # marshalling would otherwise sit inside the timed region: about 15 us per
+    # per-mesh call, about 0.1 ms for the batch's 512 output pointers); the
+    # same with per-call marshalling is reported beside them
+    def plain_python():
         for i, d in enumerate(dms):
             lf.lfem_assemble(d.handle, d.pattern, what, None, None, vals[2 * i], vals[2 * i + 1], None,
                              lf.LFEM_SCATTER_BLOCKED, stream)
 
+    calls = [lf.prepare_assemble(d.handle, d.pattern, what, None, None, vals[2 * i], vals[2 * i + 1], None,
+                                 lf.LFEM_SCATTER_BLOCKED, stream) for i, d in enumerate(dms)]
+
+    def plain():
+        for c in calls:
+            c()
+
     b = lf.lfem_batch_create([d.handle for d in dms], [d.pattern for d in dms], what, 1)
+    outs = lf.BatchOutputs(vals)
+
+    def batched_python():
+        lf.lfem_assemble_batch(b, vals, stream)
 
     def batched():
-        lf.lfem_assemble_batch(b, vals, stream)
+        lf.lfem_assemble_batch(b, outs, stream)
 
     def best(fn):
         fn()
@@ -147,10 +162,13 @@ def batched_vs_plain(lf, torch, meshgen, reps=5):
 
     t_plain = best(plain)   # per-mesh schedules as tuned by the batch
     t_batch = best(batched)
+    t_plain_py = best(plain_python)
+    t_batch_py = best(batched_python)
     T = sum(d.T for d in dms)
     res = {"meshes": len(dms), "elements": T, "nnz": sum(d.nnz for d in dms), "matrices": "M+A",
            "plain_ms": t_plain, "batched_ms": t_batch, "speedup": t_plain / t_batch,
-           "batched_elements_per_s": T / (t_batch * 1e-3)}
+           "batched_elements_per_s": T / (t_batch * 1e-3),
+           "plain_ms_marshalled_per_call": t_plain_py, "batched_ms_marshalled_per_call": t_batch_py}
     lf.lfem_batch_destroy(b)
     for d in dms:
         d.close()

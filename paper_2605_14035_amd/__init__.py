@@ -32,7 +32,8 @@ __all__ = [
     "lfem_pattern_info", "lfem_assemble", "lfem_assemble_mass", "lfem_assemble_stiffness", "lfem_assemble_weighted",
     "lfem_pattern_autotune", "lfem_pattern_autotune_ex", "lfem_tune_cache_clear", "lfem_pattern_schedule", "lfem_batch_create", "lfem_batch_create_ex", "lfem_assemble_batch", "lfem_shape_grad",
     "lfem_shape_grad_noalloc", "lfem_energy", "lfem_assemble_load", "lfem_assemble_kll", "lfem_spmv", "lfem_dziuk_system", "lfem_kll_system", "lfem_reference_table", "lfem_status_get", "lfem_status_reset", "lfem_last_error", "lfem_version", "lfem_set_debug",
-    "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device",
+    "lfem_mesh_destroy", "lfem_pattern_destroy", "lfem_batch_destroy", "copy_from_device", "BatchOutputs",
+    "prepare_assemble",
     "library_path",
 ]
 
@@ -211,11 +212,41 @@ def lfem_batch_create_ex(meshes, patterns, what: int, coef_a=None, coef_c=None, 
     return out
 
 
+class BatchOutputs:
+    """The output pointer array of a batch, marshalled once: a flat list of
+    float64 device tensors (mesh-major, ordered M, A, MC within a mesh) and
+    the C array of their addresses.  Keeps the tensors referenced; pass it to
+    lfem_assemble_batch in place of the list to skip the per-call marshalling
+    (a repeated time step writes the same outputs)."""
+
+    def __init__(self, vals):
+        self.vals = list(vals)
+        self.array = (C.c_void_p * len(self.vals))(*[_ptr(v, torch.float64, "vals").value for v in self.vals])
+
+
 def lfem_assemble_batch(batch, vals, stream=None):
     """vals: flat list of float64 device tensors, mesh-major, ordered M, A, MC
-    within a mesh."""
-    arr = (C.c_void_p * len(vals))(*[_ptr(v, torch.float64, "vals").value for v in vals])
+    within a mesh, or a BatchOutputs built from such a list."""
+    arr = vals.array if isinstance(vals, BatchOutputs) else BatchOutputs(vals).array
     _lib.check(_L.lfem_assemble_batch(batch, arr, _stream(stream)), "lfem_assemble_batch")
+
+
+def prepare_assemble(mesh, pattern, what: int, coef_a=None, coef_c=None, vals_m=None, vals_a=None,
+                     vals_mc=None, scatter: int = LFEM_SCATTER_AUTO, stream=None):
+    """lfem_assemble with its arguments marshalled once: returns a callable
+    that issues the same call (same tensors, stream and scatter) each time it
+    is called.  The tensors stay referenced by the callable."""
+    keep = (coef_a, coef_c, vals_m, vals_a, vals_mc)
+    args = (mesh, pattern, int(what), _ptr(coef_a, torch.float64, "coef_a"), _ptr(coef_c, torch.float64, "coef_c"),
+            _ptr(vals_m, torch.float64, "vals_m"), _ptr(vals_a, torch.float64, "vals_a"),
+            _ptr(vals_mc, torch.float64, "vals_mc"), int(scatter), _stream(stream))
+    fn = _L.lfem_assemble
+
+    def call():
+        _lib.check(fn(*args), "lfem_assemble")
+
+    call.keep = keep
+    return call
 
 
 def lfem_shape_grad(mesh, u, v, alpha, w, z, beta, grad, stream=None):

@@ -356,3 +356,32 @@ def test_batch_member_state_changes(lf):
     lf.lfem_batch_destroy(b)
     for d in dms:
         d.close()
+
+
+def test_prebuilt_arguments(lf):
+    """BatchOutputs (the output pointer array marshalled once) and
+    prepare_assemble (a per-mesh call marshalled once) give the same bits as
+    the per-call forms."""
+    ms = mixed_meshes()[:4]
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w)
+    outs = lf.BatchOutputs([torch.full_like(v, float("nan")) for v in vals])
+    lf.lfem_assemble_batch(b, outs)
+    lf.lfem_assemble_batch(b, outs)
+    torch.cuda.synchronize()
+    for r, v in zip(vals, outs.vals):
+        assert torch.equal(r, v)
+    for i, d in enumerate(dms):
+        vm = torch.full((d.nnz,), float("nan"), dtype=torch.float64, device="cuda")
+        va = torch.full_like(vm, float("nan"))
+        call = lf.prepare_assemble(d.handle, d.pattern, w, None, None, vm, va, None, lf.LFEM_SCATTER_BLOCKED)
+        call()
+        call()
+        torch.cuda.synchronize()
+        assert torch.equal(vm, vals[2 * i][:d.nnz]) and torch.equal(va, vals[2 * i + 1][:d.nnz])
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
