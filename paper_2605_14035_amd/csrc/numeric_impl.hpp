@@ -871,8 +871,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             LFEM_HIP(hipGetLastError());
         }
         return;
-    }
-    if constexpr (E::d == 3 && E::p >= 3) {
+    } else if constexpr (E::d == 3 && E::p >= 3) {
         // one wave per element; staged (also for a blocked request: no block
         // schedule for orders above 2) or atomic
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
