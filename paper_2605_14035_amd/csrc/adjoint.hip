@@ -73,7 +73,9 @@ __global__ __launch_bounds__(256) void k_adjoint(
     const double *__restrict__ z, double beta, double *__restrict__ out,
     unsigned long long *__restrict__ degenerate)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous element ranges per XCD: neighbouring elements share nodes,
+    // whose gathers then read their staged values from one L2
+    const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (e >= T) return;
     const bool has_a = u && v && alpha != 0.0;
     const bool has_m = w && z && beta != 0.0;
@@ -184,7 +186,9 @@ __global__ __launch_bounds__(256) void k_load(const double *__restrict__ coords,
                                               const double *__restrict__ f, double *__restrict__ out,
                                               unsigned long long *__restrict__ degenerate)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous element ranges per XCD: neighbouring elements share nodes,
+    // whose gathers then read their staged values from one L2
+    const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (e >= T) return;
     int32_t nid[E::k];
     double x[E::n][E::k], fe[E::k], acc[E::k];
@@ -228,7 +232,9 @@ __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, 
                                              double *__restrict__ out, unsigned long long *__restrict__ degenerate)
 {
     constexpr int NC = E::n + 1;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous element ranges per XCD: neighbouring elements share nodes,
+    // whose gathers then read their staged values from one L2
+    const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (e >= T) return;
     int32_t nid[E::k];
     double x[E::n][E::k], ul[NC][E::k], acc[NC][E::k];
@@ -300,7 +306,8 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T,
                                                 double *__restrict__ grad)
 {
     constexpr int U = 8;  // incidences in flight per thread
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    // contiguous node ranges per XCD (the staging kernels map elements the same way)
+    const int64_t r = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (r >= N) return;
     double acc[NCH];
 #pragma unroll

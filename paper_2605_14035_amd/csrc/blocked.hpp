@@ -210,15 +210,6 @@ __device__ __forceinline__ double local_value(int mat, int a, int b,
     return mat < NM ? LM[mat][p] : LA[p];
 }
 
-// Workgroup i runs on XCD i % 8; give each XCD a contiguous range of blocks so
-// that neighbouring blocks (which share halo elements and nodes) share an L2.
-__device__ __forceinline__ int xcd_block(int bid, int nb)
-{
-    const int per = nb >> 3, rem = nb & 7;
-    const int xcd = bid & 7, local = bid >> 3;
-    return xcd * per + min(xcd, rem) + local;
-}
-
 // add the contributions whose "ordered" bit equals ORDERED into the LDS block
 template <class E, int NM, bool HA, bool ORDERED, int KW, int MW>
 __device__ __forceinline__ void scatter_lds(const int32_t (&rb)[E::k], const uint32_t (&ow)[KW],

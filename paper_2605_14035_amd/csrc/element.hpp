@@ -71,6 +71,15 @@ struct ET {
     using B = RefBasis<D, (P <= 2 ? P : 1)>;  // used only when affine_j
 };
 
+// Workgroup i runs on XCD i % 8; give each XCD a contiguous range of blocks so
+// that neighbouring blocks (which share halo elements and nodes) share an L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb)
+{
+    const int per = nb >> 3, rem = nb & 7;
+    const int xcd = bid & 7, local = bid >> 3;
+    return xcd * per + min(xcd, rem) + local;
+}
+
 // Read-only tables are read through the constant address space: uniform loads
 // from it become scalar loads.
 using cdouble = const __attribute__((address_space(4))) double;
