@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
                                                 const int32_t *__restrict__ row_ptr,
                                                 const uint8_t *__restrict__ off8, int kkp)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (e >= T) return;
     constexpr int NMAT = NM + (HA ? 1 : 0);
     int32_t nid[E::k];
@@ -261,11 +261,14 @@ __global__ __launch_bounds__(64 * kWaveElems) void k_wave(const BlockArgs g, int
             }
         __syncthreads();
     }
+    // workgroups in launch order (an XCD-aware mapping leaves whole XCDs idle
+    // in a partial last round)
+    const int64_t gb = blockIdx.x;
     for (int64_t it = 0; it < iters; ++it) {
         const int cb = static_cast<int>(it & 1), nb = cb ^ 1;
-        const int64_t e = (it * gridDim.x + blockIdx.x) * W + wave;
+        const int64_t e = (it * gridDim.x + gb) * W + wave;
         const bool active = e < T;
-        const int64_t en = ((it + 1) * gridDim.x + blockIdx.x) * W + wave;
+        const int64_t en = ((it + 1) * gridDim.x + gb) * W + wave;
         const bool nact = it + 1 < iters && en < T;
         int32_t nid_next = 0;
         if (nact && lane < K) nid_next = conn[lane * T + en];
@@ -466,8 +469,9 @@ __global__ __launch_bounds__(256) void k_wave_tri(const BlockArgs g, int64_t T, 
     const int64_t per = static_cast<int64_t>(gridDim.x) * W * EW;
     const int64_t iters = (T + per - 1) / per;  // the same in every wave: uniform barriers
     const int li = lane & 15, lk = lane >> 4;
+    const int64_t gb = blockIdx.x;  // launch order: a partial last round keeps every XCD busy
     for (int64_t it = 0; it < iters; ++it) {
-        const int64_t e0 = ((it * gridDim.x + blockIdx.x) * W + wave) * EW;  // this wave's first element
+        const int64_t e0 = ((it * gridDim.x + gb) * W + wave) * EW;  // this wave's first element
         __syncthreads();  // reference table in place; the previous elements' data consumed
         for (int i = lane; i < EW * K; i += 64) {
             const int j = i / K, a = i - j * K;

@@ -17,6 +17,7 @@
 // in place.
 #include <algorithm>
 
+#include "element.hpp"
 #include "lfem_internal.hpp"
 
 namespace lfem {
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(256) void k_step_rows(int64_t n_rows, const int32_t
                                                    const double *__restrict__ f, double alpha,
                                                    double *__restrict__ s, double *__restrict__ rhs)
 {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t r = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
     double acc[NC];
 #pragma unroll
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n_rows, const int32_t *__r
                                               const int32_t *__restrict__ col, const double *__restrict__ v,
                                               const double *__restrict__ x, double alpha, double *__restrict__ y)
 {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t r = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
     double acc[NC];
 #pragma unroll
