@@ -135,13 +135,17 @@ lfem_status lfem_mesh_set_coords(lfem_mesh_t m, const double *coords);
  * Symbolic phase (once per topology): build the CSR pattern, the
  * element -> CSR slot map (one byte per local pair: the column offset inside
  * the row; two bytes for elements of more than 15 nodes, the cubic and
- * quartic tetrahedra) and the row-block schedule of the blocked scatter.  The pattern is
+ * quartic tetrahedra, and for any mesh with a row of more than 255 entries, a
+ * node of very high valence) and the row-block schedule of the blocked
+ * scatter.  A pattern with two-byte slots has no block schedule: its
+ * LFEM_SCATTER_AUTO choice is the staged scatter, lfem_assemble runs a
+ * blocked request staged, and lfem_pattern_schedule refuses the blocked
+ * scatter with LFEM_EUNSUPPORTED.  The pattern is
  * the structural sparsity of the element array (the paper's sparse() step
  * without its value-dependent dropping).  SYNCHRONISES stream once to learn
  * nnz and to build the block schedule on the host.
  * Errors: LFEM_EINVAL (a conn entry outside [0, N) or repeated inside an
- * element), LFEM_ERANGE (nnz >= 2^31, or a row with more than 255 entries,
- * 1023 for elements of more than 15 nodes),
+ * element), LFEM_ERANGE (nnz >= 2^31, or a row with more than 1023 entries),
  * LFEM_ENOMEM, LFEM_EHIP.
  */
 lfem_status lfem_pattern_build(lfem_mesh_t m, void *stream, lfem_pattern_t *out);
@@ -162,6 +166,7 @@ typedef struct {
     int32_t max_colors;       /* colours used inside one block */
     double halo;              /* element evaluations per element (>= 1) */
     int32_t scatter;          /* variant used by LFEM_SCATTER_AUTO */
+    int32_t slot_bytes;       /* bytes per local pair in the slot map: 1 or 2 */
 } lfem_pattern_info_t;
 
 lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
@@ -173,8 +178,9 @@ lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
  * weighted mass (required with LFEM_MC).  vals_m / vals_a / vals_mc: outputs
  * of nnz doubles each, overwritten (required for the selected matrices).
  * scatter: LFEM_SCATTER_*.  The blocked and staged scatters are bitwise
- * reproducible run to run; the atomic one is not.  Orders 3 and 4 have no
- * block schedule: a blocked request takes the staged scatter.  The first
+ * reproducible run to run; the atomic one is not.  Orders 3 and 4, and
+ * patterns with rows of more than 255 entries, have no block schedule: a
+ * blocked request takes the staged scatter.  The first
  * staged call on a pattern builds its contribution lists and SYNCHRONISES
  * stream once (LFEM_EUNSUPPORTED if k^2 * n_elems >= 2^31); later calls are
  * asynchronous and allocate nothing while the staging buffer suffices.

@@ -51,7 +51,7 @@ class PatternInfo(C.Structure):
     _fields_ = [("n_rows", C.c_int64), ("nnz", C.c_int64), ("max_row", C.c_int32),
                 ("blocks", C.c_int32), ("block_cap", C.c_int32), ("max_block_rows", C.c_int32),
                 ("max_block_elems", C.c_int32), ("max_colors", C.c_int32), ("halo", C.c_double),
-                ("scatter", C.c_int32)]
+                ("scatter", C.c_int32), ("slot_bytes", C.c_int32)]
 
 
 class LfemError(RuntimeError):

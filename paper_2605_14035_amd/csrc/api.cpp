@@ -240,6 +240,7 @@ lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info)
         info->max_colors = p->sched.max_colors;
         info->halo = p->sched.halo;
         info->scatter = p->tuned_variant;
+        info->slot_bytes = p->off16 ? 2 : 1;
     });
 }
 

@@ -44,10 +44,20 @@ namespace {
 // values with FP64 atomics (formed pair by pair, or accumulated point by point
 // for tetrahedra)
 // ---------------------------------------------------------------------------
+// column offset of local pair (a, b) of element e: byte slot map (stride kkp)
+// or, for patterns with rows longer than 255 entries, the 16-bit one
+template <int K>
+__device__ __forceinline__ int32_t pair_slot(const uint8_t *__restrict__ off8, const uint16_t *__restrict__ off16,
+                                             int kkp, int64_t e, int a, int b)
+{
+    return off16 ? static_cast<int32_t>(off16[(e * K + a) * K + b]) : static_cast<int32_t>(off8[e * kkp + a * K + b]);
+}
+
 template <class E, int Q, int NM, bool HA>
 __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
                                                 const int32_t *__restrict__ row_ptr,
-                                                const uint8_t *__restrict__ off8, int kkp)
+                                                const uint8_t *__restrict__ off8,
+                                                const uint16_t *__restrict__ off16, int kkp)
 {
     const int64_t e = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (e >= T) return;
@@ -57,7 +67,6 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
     for (int a = 0; a < E::k; ++a) nid[a] = conn[a * T + e];
     double x[E::n][E::k];
     gather_coords<E>(nid, g.coords, g.N, x);
-    const uint8_t *o = off8 + e * kkp;
     if constexpr (E::d == 3) {
         // tetrahedra: accumulate the local matrices point by point (see k_stage)
         double LM[NM > 0 ? NM : 1][E::np], LA[E::np];
@@ -70,7 +79,8 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
             for (int b = 0; b < E::k; ++b)
 #pragma unroll
                 for (int mat = 0; mat < NMAT; ++mat)
-                    unsafeAtomicAdd(g.v[mat] + rb + o[a * E::k + b], local_value<E, NM, HA>(mat, a, b, LM, LA));
+                    unsafeAtomicAdd(g.v[mat] + rb + pair_slot<E::k>(off8, off16, kkp, e, a, b),
+                                    local_value<E, NM, HA>(mat, a, b, LM, LA));
         }
         return;
     }
@@ -85,11 +95,11 @@ __global__ __launch_bounds__(256) void k_atomic(const BlockArgs g, int64_t T, co
         for (int b = a; b < E::k; ++b, ++p) {
             double v[NMAT];
             pair_values<E, Q, NM, HA>(p, f, kq, g.tabp, v);
-            const int32_t sa = row_ptr[nid[a]] + o[a * E::k + b];
+            const int32_t sa = row_ptr[nid[a]] + pair_slot<E::k>(off8, off16, kkp, e, a, b);
 #pragma unroll
             for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sa, v[mat]);
             if (a != b) {
-                const int32_t sb = row_ptr[nid[b]] + o[b * E::k + a];
+                const int32_t sb = row_ptr[nid[b]] + pair_slot<E::k>(off8, off16, kkp, e, b, a);
 #pragma unroll
                 for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sb, v[mat]);
             }
@@ -441,11 +451,12 @@ __global__ __launch_bounds__(64 * kWaveElems) void k_wave(const BlockArgs g, int
 //   M_ab = sum_q (f_q phi_a(xi_q)) phi_b(xi_q)              (Q inner terms),
 // on FP64 MFMA, the four elements' chains interleaved.  The values of the
 // pairs a <= b are staged element by element, or with ATOMIC added to the CSR
-// values through the byte slot map.
+// values through the slot map.
 template <class E, int Q, int NM, bool HA, bool ATOMIC>
 __global__ __launch_bounds__(256) void k_wave_tri(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
                                                   double *__restrict__ stage, const int32_t *__restrict__ row_ptr,
-                                                  const uint8_t *__restrict__ off8, int kkp)
+                                                  const uint8_t *__restrict__ off8,
+                                                  const uint16_t *__restrict__ off16, int kkp)
 {
     constexpr int K = E::k, D = E::d, NA = E::n, NP = E::np, NMAT = NM + (HA ? 1 : 0);
     constexpr int RS = 1 + K + K * D;  // per point: weight, phi (K), grad phi (K x D)
@@ -585,11 +596,11 @@ __global__ __launch_bounds__(256) void k_wave_tri(const BlockArgs g, int64_t T, 
                 for (int s = 0; s < NM; ++s) v[s] = accM[s][j][rr];
                 if constexpr (HA) v[NM] = accA[j][rr];
                 if constexpr (ATOMIC) {
-                    const int32_t sab = row_ptr[nid[wave][j][a]] + off8[e * kkp + a * K + b];
+                    const int32_t sab = row_ptr[nid[wave][j][a]] + pair_slot<K>(off8, off16, kkp, e, a, b);
 #pragma unroll
                     for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sab, v[mat]);
                     if (a != b) {
-                        const int32_t sba = row_ptr[nid[wave][j][b]] + off8[e * kkp + b * K + a];
+                        const int32_t sba = row_ptr[nid[wave][j][b]] + pair_slot<K>(off8, off16, kkp, e, b, a);
 #pragma unroll
                         for (int mat = 0; mat < NMAT; ++mat) unsafeAtomicAdd(g.v[mat] + sba, v[mat]);
                     }
@@ -846,7 +857,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
                 k_fill_zero<<<grid_for(p.nnz, 256), 256, 0, s>>>(o.v[mat], p.nnz);
             with_rule<E>(m.Q, [&](auto qc) {
                 k_wave_tri<E, decltype(qc)::value, NM, HA, true><<<grid, 256, 0, s>>>(g, m.T, m.conn, nullptr,
-                                                                                    p.row_ptr, p.off8, p.kkp);
+                                                                                    p.row_ptr, p.off8, p.off16, p.kkp);
             });
             LFEM_HIP(hipGetLastError());
             return;
@@ -862,7 +873,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         }
         with_rule<E>(m.Q, [&](auto qc) {
             k_wave_tri<E, decltype(qc)::value, NM, HA, false><<<grid, 256, 0, s>>>(g, m.T, m.conn, p.stage,
-                                                                                 p.row_ptr, p.off8, p.kkp);
+                                                                                 p.row_ptr, p.off8, p.off16, p.kkp);
         });
         LFEM_HIP(hipGetLastError());
         k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
@@ -922,7 +933,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
         with_rule<E>(m.Q, [&](auto qc) {
             k_atomic<E, decltype(qc)::value, NM, HA><<<grid_for(m.T, 256), 256, 0, s>>>(g, m.T, m.conn, p.row_ptr,
-                                                                                       p.off8, p.kkp);
+                                                                                       p.off8, p.off16, p.kkp);
         });
         LFEM_HIP(hipGetLastError());
         return;

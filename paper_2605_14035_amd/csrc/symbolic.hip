@@ -454,27 +454,33 @@ void build_pattern(Mesh &m, Pattern &p, hipStream_t s)
     LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&rowlen), (m.N + 1) * sizeof(int32_t), s));
     LFEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&tot), sizeof(int64_t), s));
     p.row_ptr = dev_alloc<int32_t>(m.N + 1);
-    const bool wide = m.k > kMaxNodes8;
-    const int row_cap = wide ? kMaxRowWide : ROW_MAX;
-    if (m.N > 0) {
-        if (wide)
-            k_rows<0, kMaxRowWide, ROW_NT_WIDE><<<grid_for(m.N, ROW_NT_WIDE), ROW_NT_WIDE, 0, s>>>(
-                m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen, nullptr, nullptr, m.flags);
-        else
-            k_rows<0><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen,
-                                                               nullptr, nullptr, m.flags);
-        LFEM_HIP(hipGetLastError());
-    }
-    exclusive_scan_i32(rowlen, p.row_ptr, m.N, tot, s);
+    // elements of up to kMaxNodes8 nodes first try rows of at most 255
+    // entries (byte slot maps, every scatter); a longer row (a node of very
+    // high valence) switches the pattern to the 16-bit slot map and rows of up
+    // to kMaxRowWide entries, which the staged and atomic scatters take
+    bool wide = m.k > kMaxNodes8;
     int64_t nnz = 0;
-    LFEM_HIP(hipMemcpyAsync(&nnz, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LFEM_HIP(hipMemcpyAsync(flags, m.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
-    LFEM_HIP(hipStreamSynchronize(s));
+    for (;;) {
+        if (m.N > 0) {
+            if (wide)
+                k_rows<0, kMaxRowWide, ROW_NT_WIDE><<<grid_for(m.N, ROW_NT_WIDE), ROW_NT_WIDE, 0, s>>>(
+                    m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen, nullptr, nullptr, m.flags);
+            else
+                k_rows<0><<<grid_for(m.N, ROW_NT), ROW_NT, 0, s>>>(m.N, m.k, m.T, m.conn, m.ne_ptr, m.ne, rowlen,
+                                                                   nullptr, nullptr, m.flags);
+            LFEM_HIP(hipGetLastError());
+        }
+        exclusive_scan_i32(rowlen, p.row_ptr, m.N, tot, s);
+        LFEM_HIP(hipMemcpyAsync(&nnz, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LFEM_HIP(hipMemcpyAsync(flags, m.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+        LFEM_HIP(hipStreamSynchronize(s));
+        if (!flags[2] || wide) break;
+        wide = true;
+        LFEM_HIP(hipMemsetAsync(m.flags + 2, 0, sizeof(int32_t), s));
+    }
     LFEM_HIP(hipFreeAsync(rowlen, s));
     LFEM_HIP(hipFreeAsync(tot, s));
-    LFEM_REQUIRE(!flags[2], LFEM_ERANGE,
-                 row_cap == ROW_MAX ? "a CSR row would hold more than 255 entries"
-                                    : "a CSR row would hold more than 1023 entries");
+    LFEM_REQUIRE(!flags[2], LFEM_ERANGE, "a CSR row would hold more than 1023 entries");
     LFEM_REQUIRE(nnz < (int64_t(1) << 31), LFEM_ERANGE, "nnz does not fit in int32");
     p.nnz = nnz;
     p.col_idx = dev_alloc<int32_t>(nnz);
@@ -615,6 +621,8 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
 {
     LFEM_REQUIRE(max_rows >= 1 && max_rows <= kBlockMaxRows, LFEM_EINVAL, "rows per block out of range");
     LFEM_REQUIRE(m.p <= 2, LFEM_EUNSUPPORTED, "block schedules cover orders 1 and 2");
+    LFEM_REQUIRE(p.off8 != nullptr, LFEM_EUNSUPPORTED,
+                 "block schedules need rows of at most 255 entries (byte slot maps)");
     free_schedule(p.sched);
     ++p.sched_gen;
     BlockSchedule &b = p.sched;

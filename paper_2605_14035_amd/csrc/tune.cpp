@@ -60,7 +60,8 @@ float time_variant(Mesh &m, Pattern &p, const NumericOut &o, int variant, hipStr
 }
 
 // the result cache
-using TuneKey = std::tuple<int, int, int, unsigned, int, int>;  // device, etype, Q, what, bucket, atomic
+// device, element type, rule, matrices, size bucket, atomic allowed, 16-bit slot map
+using TuneKey = std::tuple<int, int, int, unsigned, int, int, int>;
 struct TuneResult {
     int variant;
     int cap;
@@ -78,11 +79,11 @@ int size_bucket(int64_t T)
     return b;
 }
 
-TuneKey tune_key(const Mesh &m, unsigned what, bool atomic)
+TuneKey tune_key(const Mesh &m, const Pattern &p, unsigned what, bool atomic)
 {
     int dev = 0;
     LFEM_HIP(hipGetDevice(&dev));
-    return TuneKey{dev, m.etype, m.Q, what, size_bucket(m.T), atomic ? 1 : 0};
+    return TuneKey{dev, m.etype, m.Q, what, size_bucket(m.T), atomic ? 1 : 0, p.off16 ? 1 : 0};
 }
 
 // the staged scatter's size limit (its contribution codes are int32)
@@ -126,7 +127,7 @@ int autotune_pattern(Mesh &m, Pattern &p, unsigned what, unsigned flags, hipStre
 {
     if (m.T == 0 || p.nnz == 0) return p.tuned_variant;
     const bool allow_atomic = flags & LFEM_TUNE_ALLOW_ATOMIC;
-    const TuneKey key = tune_key(m, what, allow_atomic);
+    const TuneKey key = tune_key(m, p, what, allow_atomic);
     if (!(flags & LFEM_TUNE_NO_CACHE)) {
         TuneResult hit{};
         bool found = false;
