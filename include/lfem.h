@@ -117,8 +117,7 @@ typedef struct lfem_batch_s *lfem_batch_t;
  * asynchronously on stream (device buffers are allocated with hipMalloc
  * first); use the handle on the same stream, or synchronise it before using
  * the handle on another.
- * Errors: LFEM_EINVAL (sizes, nulls), LFEM_ERANGE (n_elems >= 2^25 or
- * n_elems * k >= 2^31),
+ * Errors: LFEM_EINVAL (sizes, nulls), LFEM_ERANGE (n_elems * k >= 2^31),
  * LFEM_EUNSUPPORTED (type/rule), LFEM_ENOMEM, LFEM_EHIP.
  */
 lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,

@@ -295,7 +295,8 @@ __global__ __launch_bounds__(256) void k_kll(const double *__restrict__ coords, 
         for (int c = 0; c < NC; ++c) out[(a * T + e) * NC + c] = acc[c][a];
 }
 
-// grad[c*N + r] = sum over incidences (e, a) of node r, ascending, of stage[(a*T + e)*n + c]
+// grad[c*N + r] = sum over incidences (e, a) of node r, in ascending order of
+// their codes a*T + e, of stage[(a*T + e)*n + c]
 // (one plane per local node, the n channels of a contribution side by side:
 // one cache line per incidence, coalesced writes by consecutive elements)
 template <int NCH>
@@ -322,10 +323,9 @@ __global__ __launch_bounds__(256) void k_gather(int64_t N, int64_t T,
 #pragma unroll
         for (int i = 0; i < U; ++i)
             if (i < cnt) {
-                const int64_t e = inc[i] >> kIncShift;
-                const int a = inc[i] & kIncMask;
+                const int64_t at = inc[i];  // a * T + e
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) v[i][c] = stage[(a * T + e) * NCH + c];
+                for (int c = 0; c < NCH; ++c) v[i][c] = stage[at * NCH + c];
             }
         // added in ascending incidence order, as without the batching
 #pragma unroll

@@ -131,8 +131,8 @@ lfem_status lfem_mesh_create(int domain, int dim, int order, int64_t n_nodes,
         LFEM_REQUIRE(n_nodes >= 0 && n_elems >= 0, LFEM_EINVAL, "negative size");
         LFEM_REQUIRE(n_nodes < (int64_t(1) << 31) - 1, LFEM_ERANGE, "n_nodes >= 2^31 - 1");
         const int k = nodes_per_elem(dim, order);
-        LFEM_REQUIRE(n_elems < (int64_t(1) << (31 - kIncShift)) && n_elems * k < (int64_t(1) << 31), LFEM_ERANGE,
-                     "too many elements for int32 incidence codes (at most 2^25)");
+        LFEM_REQUIRE(n_elems * k < (int64_t(1) << 31), LFEM_ERANGE,
+                     "too many element nodes for int32 incidence codes (k * n_elems >= 2^31)");
         LFEM_REQUIRE(n_nodes == 0 || coords, LFEM_EINVAL, "coords is null");
         LFEM_REQUIRE(n_elems == 0 || conn, LFEM_EINVAL, "conn is null");
         RefTable tab;

@@ -73,9 +73,6 @@ inline int etype_of(int domain, int d, int p)
 constexpr int kMaxNodes = 35;
 constexpr int kMaxNodes8 = 15;
 constexpr int kMaxRowWide = 1023;
-// incidences are coded e << kIncShift | a (local node a < 2^kIncShift)
-constexpr int kIncShift = 6;
-constexpr int kIncMask = (1 << kIncShift) - 1;
 // contributions of one CSR value loaded at once by the staged reduction; the
 // values with longer lists (diagonals of well-connected nodes) are summed by
 // a second, small launch so that the main one needs a single round of loads
@@ -124,7 +121,7 @@ struct Mesh {
     double *tabp = nullptr;          // device pair-major reference tensors
     RefTable host_tab;
     int32_t *ne_ptr = nullptr;       // [N+1] node -> incidence offsets
-    int32_t *ne = nullptr;           // [k*T] incidences e << kIncShift | a, ascending per node
+    int32_t *ne = nullptr;           // [k*T] incidences a*T + e (position in conn), ascending per node
     int32_t *flags = nullptr;        // [4] device flags: [0] bad index, [1] repeated node
     unsigned long long *degenerate = nullptr;
     double *scratch = nullptr;       // adjoint staging, grown on demand

@@ -116,9 +116,9 @@ __global__ void k_inc_fill(const int32_t *__restrict__ conn, int64_t kT, int64_t
     if (i >= kT) return;
     const int32_t node = conn[i];
     if (node < 0 || node >= N) return;
-    const int64_t a = i / T, e = i - a * T;
+    // the incidence (e, a) is coded by its position a * T + e in conn
     const int32_t pos = atomicAdd(&cursor[node], 1);
-    ne[ptr[node] + pos] = static_cast<int32_t>(e << kIncShift | a);
+    ne[ptr[node] + pos] = static_cast<int32_t>(i);
 }
 
 // sort every short list [ptr[i], ptr[i+1]) ascending (insertion sort)
@@ -158,6 +158,20 @@ constexpr int ROW_NT = 64;
 constexpr int ROW_MAX = 255;
 constexpr int ROW_NT_WIDE = 16;
 
+// element e of the incidence code c = a * T + e (0 <= a < k, c < 2^31): the
+// FP64 quotient is within 2^-21 of c / T, so truncating it is off by at most
+// one, which one correction step fixes (no 32-bit integer division per code)
+__device__ __forceinline__ int64_t inc_elem(int32_t c, int64_t T, double inv_t)
+{
+    const int64_t a = static_cast<int64_t>(static_cast<double>(c) * inv_t);
+    int64_t e = c - a * T;
+    if (e < 0)
+        e += T;
+    else if (e >= T)
+        e -= T;
+    return e;
+}
+
 template <int FILL, int RMAX = ROW_MAX, int NTR = ROW_NT>
 __global__ __launch_bounds__(NTR) void k_rows(int64_t N, int k, int64_t T,
                                                  const int32_t *__restrict__ conn,
@@ -174,8 +188,9 @@ __global__ __launch_bounds__(NTR) void k_rows(int64_t N, int k, int64_t T,
     if (i >= N) return;  // no barrier below
     int len = 0;
     bool overflow = false;
+    const double inv_t = 1.0 / static_cast<double>(T > 0 ? T : 1);
     for (int32_t s = ne_ptr[i]; s < ne_ptr[i + 1] && !overflow; ++s) {
-        const int64_t e = ne[s] >> kIncShift;
+        const int64_t e = inc_elem(ne[s], T, inv_t);
         for (int b = 0; b < k; ++b) {
             const int32_t j = conn[b * T + e];
             int lo = 0, hi = len;
@@ -690,7 +705,7 @@ void build_schedule(Mesh &m, Pattern &p, int cap, int max_rows, hipStream_t s)
             if (rp[r1 + 1] - rp[r0] + slots + add > cap) break;
             const size_t before = list.size();
             for (int32_t q = p.h_ne_ptr[r1]; q < p.h_ne_ptr[r1 + 1]; ++q) {
-                const int32_t e = p.h_ne[q] >> kIncShift;
+                const int32_t e = static_cast<int32_t>(p.h_ne[q] % T);
                 if (stamp[e] != nb) {
                     stamp[e] = nb;
                     list.push_back(e);

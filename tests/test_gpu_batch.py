@@ -9,7 +9,7 @@ import torch
 
 import meshgen
 import oracle
-from gpu_util import assert_csr_close, order_mesh
+from gpu_util import assert_csr_close, fan, order_mesh
 from meshgen import meshes as mg
 
 pytestmark = pytest.mark.gpu
@@ -221,11 +221,12 @@ def test_config4_full_batch(lf):
 def mixed_family_meshes():
     """Members inside and outside the persistent kernel's family: P1 curve and
     P2 surface (inside), a P2 surface under the 16-point rule, P2 and cubic
-    tetrahedra, a quartic planar mesh and a cubic curve (outside)."""
+    tetrahedra, a quartic planar mesh, a cubic curve and a P2 surface with a
+    row of more than 255 entries (no block schedule) (outside)."""
     out = [meshgen.small_mesh("surface", 1, 1, size=3), meshgen.small_mesh("surface", 2, 2, size=3),
            dict(meshgen.small_mesh("surface", 2, 2, size=2), quad=16),
            meshgen.small_mesh("bulk", 3, 2, size=2), order_mesh("bulk", 3, 3), order_mesh("bulk", 2, 4),
-           order_mesh("surface", 1, 3)]
+           order_mesh("surface", 1, 3), fan(120, 2, True)]  # the fan's centre row exceeds 255 entries
     rng = np.random.default_rng(7)
     for m in out:
         N = m["coords"].shape[1]

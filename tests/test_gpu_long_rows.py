@@ -5,17 +5,13 @@ oracle's bit for bit, and the staged and atomic scatters must match
 the oracle's values at the usual tolerance, for every element family that
 otherwise uses byte slot maps."""
 
-import numpy as np
 import pytest
 import torch
 
 import oracle
-from gpu_util import assert_csr_close
-from meshgen import meshes as mg
+from gpu_util import assert_csr_close, fan, star
 
 pytestmark = pytest.mark.gpu
-
-QUAD = {1: 3, 2: 6, 3: 16, 4: 16}
 
 
 @pytest.fixture(scope="module")
@@ -24,58 +20,6 @@ def lf():
         pytest.skip("no GPU")
     import paper_2605_14035_amd as lf
     return lf
-
-
-def raise_order(V, F, p, edges):
-    if p == 1:
-        return V, F
-    if p == 2:
-        V2, F2, _ = mg.p1_to_p2(V, F, edges)
-        return V2, F2
-    return mg.p1_to_pp(V, F, p, edges)
-
-
-def fan(n, p, surface, seed=0):
-    """A disk around one centre vertex shared by n triangles (two rings of n
-    vertices at radii near 1 and 2), raised to order p; on a surface the
-    points are lifted onto a cone.  The centre's row holds 1 + n (p = 1),
-    1 + 3n (p = 2), 1 + 6n (p = 3) or 1 + 10n (p = 4) entries."""
-    rng = np.random.default_rng(500 + 10 * n + p + seed)
-    t = 2 * np.pi * np.arange(n) / n
-    r1 = 1.0 + 0.05 * rng.uniform(-1, 1, n)
-    r2 = 2.0 + 0.05 * rng.uniform(-1, 1, n)
-    V = np.vstack([[0.0, 0.0], np.c_[r1 * np.cos(t), r1 * np.sin(t)], np.c_[r2 * np.cos(t), r2 * np.sin(t)]])
-    i = np.arange(n)
-    j = (i + 1) % n
-    F = np.vstack([np.c_[np.zeros(n, dtype=np.int64), 1 + i, 1 + j],
-                   np.c_[1 + i, 1 + n + i, 1 + j],
-                   np.c_[1 + j, 1 + n + i, 1 + n + j]])
-    V, F = raise_order(V, F, p, mg.TRI_EDGES)
-    if surface:
-        z = 0.4 * (2.0 - np.hypot(V[:, 0], V[:, 1]))
-        V = np.c_[V, z]
-    coords, conn = mg.to_soa(V, F)
-    domain = "surface" if surface else "bulk"
-    return dict(domain=domain, dim=2, order=p, quad=QUAD[p], coords=coords, conn=conn,
-                coef=1.0 + 0.5 * np.sin(coords[0]) * np.cos(coords[1]))
-
-
-def star(n, p):
-    """P2 (or P1) tetrahedra around one centre vertex: a polygon of n rim
-    vertices at z = 0 and two apices, 2n tetrahedra sharing the centre."""
-    rng = np.random.default_rng(900 + n + p)
-    t = 2 * np.pi * np.arange(n) / n
-    r = 1.0 + 0.05 * rng.uniform(-1, 1, n)
-    V = np.vstack([[0.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, -1.0],
-                   np.c_[r * np.cos(t), r * np.sin(t), 0.02 * rng.uniform(-1, 1, n)]])
-    i = np.arange(n)
-    j = (i + 1) % n
-    F = np.vstack([np.c_[np.zeros(n, dtype=np.int64), np.ones(n, dtype=np.int64), 3 + i, 3 + j],
-                   np.c_[np.zeros(n, dtype=np.int64), np.full(n, 2), 3 + j, 3 + i]])
-    V, F = raise_order(V, F, p, mg.TET_EDGES)
-    coords, conn = mg.to_soa(V, F)
-    return dict(domain="bulk", dim=3, order=p, quad=11 if p == 2 else 4, coords=coords, conn=conn,
-                coef=1.0 + 0.5 * np.sin(coords[0]) * np.cos(coords[1]) * coords[2])
 
 
 CASES = [("planar P1", lambda: fan(300, 1, False)),
