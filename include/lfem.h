@@ -135,7 +135,8 @@ lfem_status lfem_mesh_set_coords(lfem_mesh_t m, const double *coords);
  * element -> CSR slot map (one byte per local pair: the column offset inside
  * the row; two bytes for elements of more than 15 nodes, the cubic and
  * quartic tetrahedra, and for any mesh with a row of more than 255 entries, a
- * node of very high valence) and the row-block schedule of the blocked
+ * node of very high valence) and, except for P2 tetrahedra (whose default
+ * is the staged scatter), the row-block schedule of the blocked
  * scatter.  A pattern with two-byte slots has no block schedule: its
  * LFEM_SCATTER_AUTO choice is the staged scatter, lfem_assemble runs a
  * blocked request staged, and lfem_pattern_schedule refuses the blocked
@@ -179,7 +180,10 @@ lfem_status lfem_pattern_info(lfem_pattern_t p, lfem_pattern_info_t *info);
  * scatter: LFEM_SCATTER_*.  The blocked and staged scatters are bitwise
  * reproducible run to run; the atomic one is not.  Orders 3 and 4, and
  * patterns with rows of more than 255 entries, have no block schedule: a
- * blocked request takes the staged scatter.  The first
+ * blocked request takes the staged scatter.  P2 tetrahedra default to the
+ * staged scatter; the first blocked request on such a pattern builds its
+ * block schedule (colour mode) and SYNCHRONISES stream.
+ * The first
  * staged call on a pattern builds its contribution lists and SYNCHRONISES
  * stream once (LFEM_EUNSUPPORTED if k^2 * n_elems >= 2^31); later calls are
  * asynchronous and allocate nothing while the staging buffer suffices.

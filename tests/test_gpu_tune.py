@@ -134,3 +134,32 @@ def test_schedule_knob(lf):
     v, cap = lf.lfem_pattern_autotune_ex(dt.handle, dt.pattern, lf.LFEM_M | lf.LFEM_A, lf.LFEM_TUNE_NO_CACHE)
     assert v == lf.LFEM_SCATTER_STAGED and cap == 0
     dt.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_tetrahedra_default_scatter(lf, order):
+    """P2 tetrahedra default to the staged scatter and get no block schedule
+    at pattern build (the first blocked request builds one, colour mode); P1
+    tetrahedra keep the colour-blocked default.  Every variant matches the
+    oracle, and the default equals its variant bit for bit."""
+    import meshgen
+    m = meshgen.small_mesh("bulk", 3, order, size=3)
+    d = lf.DeviceMesh.from_dict(m)
+    d.build_pattern()
+    info = lf.lfem_pattern_info(d.pattern)
+    default = lf.LFEM_SCATTER_STAGED if order == 2 else lf.LFEM_SCATTER_BLOCKED
+    assert info["scatter"] == default
+    assert (info["blocks"] == 0) == (order == 2)
+    auto = d.assemble(lf.LFEM_M | lf.LFEM_A)
+    same = d.assemble(lf.LFEM_M | lf.LFEM_A, scatter=default)
+    assert torch.equal(auto["M"], same["M"]) and torch.equal(auto["A"], same["A"])
+    check(lf, m, d, f"P{order} tetrahedra default")
+    rp, ci = (x.cpu().numpy() for x in d.pattern_tensors())
+    for variant in (lf.LFEM_SCATTER_BLOCKED, lf.LFEM_SCATTER_STAGED):
+        out = d.assemble(lf.LFEM_M | lf.LFEM_A, scatter=variant)
+        for key, kind in (("M", "mass"), ("A", "stiffness")):
+            assert_csr_close(rp, ci, out[key].cpu().numpy(), oracle.assemble(m, kind), what=f"{variant} {key}")
+    info = lf.lfem_pattern_info(d.pattern)
+    assert info["blocks"] > 0 and info["max_colors"] > 1  # built by the blocked request
+    assert info["scatter"] == default  # the default is unchanged
+    d.close()
