@@ -89,6 +89,7 @@ void release_pattern(Pattern &p)
     dev_free(p.clist);
     dev_free(p.long_slots);
     dev_free(p.stage);
+    dev_free(p.dstage);
     free_schedule(p.sched);
 }
 

@@ -127,9 +127,18 @@ constexpr size_t stage_lds_bytes()
                               : (E::d == 3 && Q <= 11 ? size_t(NM > 0 ? NM : 1) * Q * 256 * sizeof(double) : 0);
 }
 
+// vertex v if row-major pair p is the diagonal pair (v, v) of a vertex, else -1
+template <class E>
+__host__ __device__ constexpr int vertex_of_diag_pair(int p)
+{
+    for (int v = 0; v <= E::d; ++v)
+        if (p == pair_index<E::k>(v, v)) return v;
+    return -1;
+}
+
 template <class E, int Q, int NM, bool HA>
 __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const int32_t *__restrict__ conn,
-                                           double *__restrict__ stage)
+                                           double *__restrict__ stage, double *__restrict__ dstage)
 {
     // contiguous element ranges per XCD: neighbouring elements share nodes,
     // whose coordinates then come from one L2
@@ -157,11 +166,15 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
         // point loop from the Q per-point factors, which keeps their 55
         // accumulators out of the loop's registers
         double *out = stage + e * E::np * NMAT;
+        double *dout = dstage + e * (E::d + 1) * NMAT;
         if constexpr (Q <= 11) {
             extern __shared__ double fl_lds[];
             const int bad = element_local_put<E, Q, NM, HA, 256>(
-                nid, x, g.tab, g.tabp, g.cm0, g.cm1, g.ca, fl_lds + threadIdx.x,
-                [&](int p, int mat, double v) { out[p * NMAT + mat] = v; });
+                nid, x, g.tab, g.tabp, g.cm0, g.cm1, g.ca, fl_lds + threadIdx.x, [&](int p, int mat, double v) {
+                    out[p * NMAT + mat] = v;
+                    const int vd = vertex_of_diag_pair<E>(p);
+                    if (vd >= 0) dout[vd * NMAT + mat] = v;
+                });
             if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
         } else {
             // many points: one LDS read per point and pair would dominate, and
@@ -172,7 +185,12 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
 #pragma unroll
             for (int p = 0; p < E::np; ++p)
 #pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) out[p * NMAT + mat] = mat < NM ? LM[mat][p] : LA[p];
+                for (int mat = 0; mat < NMAT; ++mat) {
+                    const double v = mat < NM ? LM[mat][p] : LA[p];
+                    out[p * NMAT + mat] = v;
+                    const int vd = vertex_of_diag_pair<E>(p);
+                    if (vd >= 0) dout[vd * NMAT + mat] = v;
+                }
         }
     } else {
         double f[NM > 0 ? NM : 1][Q];
@@ -184,16 +202,20 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
             double v[NMAT];
             pair_values<E, Q, NM, HA, TAB_LDS>(p, f, kq, tabp, v);
 #pragma unroll
-            for (int mat = 0; mat < NMAT; ++mat) stage[(e * E::np + p) * NMAT + mat] = v[mat];
+            for (int mat = 0; mat < NMAT; ++mat) {
+                stage[(e * E::np + p) * NMAT + mat] = v[mat];
+                const int vd = vertex_of_diag_pair<E>(p);
+                if (vd >= 0) dstage[(e * (E::d + 1) + vd) * NMAT + mat] = v[mat];
+            }
         }
     }
 }
 
 template <class E, int Q, int NM, bool HA>
 __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                               double *__restrict__ stage)
+                                               double *__restrict__ stage, double *__restrict__ dstage)
 {
-    stage_body<E, Q, NM, HA>(g, T, conn, stage);
+    stage_body<E, Q, NM, HA>(g, T, conn, stage, dstage);
 }
 
 // the same for P2 tetrahedra under rules of up to 11 points, held to at most
@@ -202,9 +224,9 @@ __global__ __launch_bounds__(256) void k_stage(const BlockArgs g, int64_t T, con
 // the 64^3 Kuhn cube, M and A_a
 template <class E, int Q, int NM, bool HA>
 __global__ __launch_bounds__(256, 2) void k_stage2(const BlockArgs g, int64_t T, const int32_t *__restrict__ conn,
-                                                   double *__restrict__ stage)
+                                                   double *__restrict__ stage, double *__restrict__ dstage)
 {
-    stage_body<E, Q, NM, HA>(g, T, conn, stage);
+    stage_body<E, Q, NM, HA>(g, T, conn, stage, dstage);
 }
 
 // Orders 3 and 4 on tetrahedra: 20 and 35 nodes, 210 and 630 local pairs,
@@ -616,10 +638,11 @@ __global__ __launch_bounds__(256) void k_wave_tri(const BlockArgs g, int64_t T, 
 
 // sum of the contributions of CSR value s, in ascending element order, up to
 // kReduceBatch loads in flight
-template <int K, int NMAT>
+template <int K, int NMAT, int NV = 0>
 __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t c_end,
                                             const int32_t *__restrict__ clist,
-                                            const double *__restrict__ stage, double *const (&outs)[3])
+                                            const double *__restrict__ stage, double *const (&outs)[3],
+                                            const double *__restrict__ dstage = nullptr)
 {
     constexpr int NP = K * (K + 1) / 2;
     constexpr int U = kReduceBatch;
@@ -639,8 +662,13 @@ __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t 
                 const int ab = code[i] - static_cast<int>(e) * (K * K);
                 const int a = ab / K, bb = ab - a * K;
                 const int p = pair_index<K>(a, bb);
+                if (NV > 0 && a == bb && a < NV) {
 #pragma unroll
-                for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = stage[(e * NP + p) * NMAT + mat];
+                    for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = dstage[(e * NV + a) * NMAT + mat];
+                } else {
+#pragma unroll
+                    for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = stage[(e * NP + p) * NMAT + mat];
+                }
             }
 #pragma unroll
         for (int i = 0; i < U; ++i)
@@ -680,11 +708,12 @@ __global__ __launch_bounds__(256) void k_reduce(int64_t nnz, const int32_t *__re
 }
 
 // one thread per listed CSR value with a long list (same order of summation)
-template <int K, int NMAT>
+template <int K, int NMAT, int NV>
 __global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_t *__restrict__ slots,
                                                      const int32_t *__restrict__ cptr,
                                                      const int32_t *__restrict__ clist,
                                                      const double *__restrict__ stage,
+                                                     const double *__restrict__ dstage,
                                                      double *__restrict__ v0, double *__restrict__ v1,
                                                      double *__restrict__ v2)
 {
@@ -692,7 +721,7 @@ __global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_
     if (i >= nlong) return;
     const int64_t s = slots[i];
     double *const outs[3] = {v0, v1, v2};
-    reduce_slot<K, NMAT>(s, cptr[s], cptr[s + 1], clist, stage, outs);
+    reduce_slot<K, NMAT, NV>(s, cptr[s], cptr[s + 1], clist, stage, outs, dstage);
 }
 
 template <class E, int NM, bool HA, int NT>
@@ -880,9 +909,9 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
                                                                    o.v[1], o.v[2]);
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
-            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
-                                                                             p.clist, p.stage, o.v[0], o.v[1],
-                                                                             o.v[2]);
+            k_reduce_long<E::k, NMAT, 0><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
+                                                                                p.clist, p.stage, nullptr, o.v[0],
+                                                                                o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
         return;
@@ -920,9 +949,9 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
                                                                    o.v[1], o.v[2]);
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
-            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
-                                                                             p.clist, p.stage, o.v[0], o.v[1],
-                                                                             o.v[2]);
+            k_reduce_long<E::k, NMAT, 0><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
+                                                                                p.clist, p.stage, nullptr, o.v[0],
+                                                                                o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
         return;
@@ -948,6 +977,14 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.stage), need));
             p.stage_bytes = need;
         }
+        const size_t dneed = static_cast<size_t>(NMAT) * (E::d + 1) * m.T * sizeof(double);
+        if (p.dstage_bytes < dneed) {
+            dev_free(p.dstage);
+            p.dstage = nullptr;
+            p.dstage_bytes = 0;
+            LFEM_HIP(hipMalloc(reinterpret_cast<void **>(&p.dstage), dneed));
+            p.dstage_bytes = dneed;
+        }
         const BlockArgs g = block_args(m, p, o.cm0, o.cm1, o.ca, o.v[0], o.v[1], o.v[2]);
         with_rule<E>(m.Q, [&](auto qc) {
             constexpr int Q = decltype(qc)::value;
@@ -957,16 +994,15 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
             };
             auto ks = pick();
             allow_lds(reinterpret_cast<const void *>(ks), stage_lds_bytes<E, Q, NM>());
-            ks<<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q, NM>(), s>>>(g, m.T, m.conn, p.stage);
+            ks<<<grid_for(m.T, 256), 256, stage_lds_bytes<E, Q, NM>(), s>>>(g, m.T, m.conn, p.stage, p.dstage);
         });
         LFEM_HIP(hipGetLastError());
         k_reduce<E::k, NMAT><<<grid_for(p.nnz, 256), 256, 0, s>>>(p.nnz, p.cptr, p.clist, p.stage, o.v[0],
                                                                    o.v[1], o.v[2]);
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
-            k_reduce_long<E::k, NMAT><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
-                                                                             p.clist, p.stage, o.v[0], o.v[1],
-                                                                             o.v[2]);
+            k_reduce_long<E::k, NMAT, E::d + 1><<<grid_for(p.nlong, 256), 256, 0, s>>>(
+                p.nlong, p.long_slots, p.cptr, p.clist, p.stage, p.dstage, o.v[0], o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
         return;
