@@ -179,7 +179,7 @@ struct Pattern {
     int64_t nlong = 0;
     double *stage = nullptr;
     size_t stage_bytes = 0;
-    // the vertices' diagonal values of every element, [T][d + 1][NMAT] (orders
+    // the vertices' diagonal values of every element, [d + 1][T][NMAT] (orders
     // 1 and 2): the long lists read these instead of the full records
     double *dstage = nullptr;
     size_t dstage_bytes = 0;

@@ -166,14 +166,14 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
         // point loop from the Q per-point factors, which keeps their 55
         // accumulators out of the loop's registers
         double *out = stage + e * E::np * NMAT;
-        double *dout = dstage + e * (E::d + 1) * NMAT;
+        double *dout = dstage + e * NMAT;  // vertex v at dout[v * T * NMAT]
         if constexpr (Q <= 11) {
             extern __shared__ double fl_lds[];
             const int bad = element_local_put<E, Q, NM, HA, 256>(
                 nid, x, g.tab, g.tabp, g.cm0, g.cm1, g.ca, fl_lds + threadIdx.x, [&](int p, int mat, double v) {
                     out[p * NMAT + mat] = v;
                     const int vd = vertex_of_diag_pair<E>(p);
-                    if (vd >= 0) dout[vd * NMAT + mat] = v;
+                    if (vd >= 0) dout[vd * T * NMAT + mat] = v;
                 });
             if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
         } else {
@@ -189,7 +189,7 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
                     const double v = mat < NM ? LM[mat][p] : LA[p];
                     out[p * NMAT + mat] = v;
                     const int vd = vertex_of_diag_pair<E>(p);
-                    if (vd >= 0) dout[vd * NMAT + mat] = v;
+                    if (vd >= 0) dout[vd * T * NMAT + mat] = v;
                 }
         }
     } else {
@@ -205,7 +205,7 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
             for (int mat = 0; mat < NMAT; ++mat) {
                 stage[(e * E::np + p) * NMAT + mat] = v[mat];
                 const int vd = vertex_of_diag_pair<E>(p);
-                if (vd >= 0) dstage[(e * (E::d + 1) + vd) * NMAT + mat] = v[mat];
+                if (vd >= 0) dstage[(vd * T + e) * NMAT + mat] = v[mat];
             }
         }
     }
@@ -642,7 +642,7 @@ template <int K, int NMAT, int NV = 0>
 __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t c_end,
                                             const int32_t *__restrict__ clist,
                                             const double *__restrict__ stage, double *const (&outs)[3],
-                                            const double *__restrict__ dstage = nullptr)
+                                            const double *__restrict__ dstage = nullptr, int64_t T = 0)
 {
     constexpr int NP = K * (K + 1) / 2;
     constexpr int U = kReduceBatch;
@@ -664,7 +664,7 @@ __device__ __forceinline__ void reduce_slot(int64_t s, int32_t c_begin, int32_t 
                 const int p = pair_index<K>(a, bb);
                 if (NV > 0 && a == bb && a < NV) {
 #pragma unroll
-                    for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = dstage[(e * NV + a) * NMAT + mat];
+                    for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = dstage[(a * T + e) * NMAT + mat];
                 } else {
 #pragma unroll
                     for (int mat = 0; mat < NMAT; ++mat) v[i][mat] = stage[(e * NP + p) * NMAT + mat];
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_
                                                      const int32_t *__restrict__ cptr,
                                                      const int32_t *__restrict__ clist,
                                                      const double *__restrict__ stage,
-                                                     const double *__restrict__ dstage,
+                                                     const double *__restrict__ dstage, int64_t T,
                                                      double *__restrict__ v0, double *__restrict__ v1,
                                                      double *__restrict__ v2)
 {
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) void k_reduce_long(int64_t nlong, const int32_
     if (i >= nlong) return;
     const int64_t s = slots[i];
     double *const outs[3] = {v0, v1, v2};
-    reduce_slot<K, NMAT, NV>(s, cptr[s], cptr[s + 1], clist, stage, outs, dstage);
+    reduce_slot<K, NMAT, NV>(s, cptr[s], cptr[s + 1], clist, stage, outs, dstage, T);
 }
 
 template <class E, int NM, bool HA, int NT>
@@ -910,7 +910,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
             k_reduce_long<E::k, NMAT, 0><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
-                                                                                p.clist, p.stage, nullptr, o.v[0],
+                                                                                p.clist, p.stage, nullptr, 0, o.v[0],
                                                                                 o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
@@ -950,7 +950,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
             k_reduce_long<E::k, NMAT, 0><<<grid_for(p.nlong, 256), 256, 0, s>>>(p.nlong, p.long_slots, p.cptr,
-                                                                                p.clist, p.stage, nullptr, o.v[0],
+                                                                                p.clist, p.stage, nullptr, 0, o.v[0],
                                                                                 o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
@@ -1002,7 +1002,7 @@ void run(Mesh &m, Pattern &p, const Outs &o, int variant, hipStream_t s)
         LFEM_HIP(hipGetLastError());
         if (p.nlong > 0) {
             k_reduce_long<E::k, NMAT, E::d + 1><<<grid_for(p.nlong, 256), 256, 0, s>>>(
-                p.nlong, p.long_slots, p.cptr, p.clist, p.stage, p.dstage, o.v[0], o.v[1], o.v[2]);
+                p.nlong, p.long_slots, p.cptr, p.clist, p.stage, p.dstage, m.T, o.v[0], o.v[1], o.v[2]);
             LFEM_HIP(hipGetLastError());
         }
         return;
