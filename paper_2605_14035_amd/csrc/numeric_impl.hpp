@@ -166,14 +166,13 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
         // point loop from the Q per-point factors, which keeps their 55
         // accumulators out of the loop's registers
         double *out = stage + e * E::np * NMAT;
-        double *dout = dstage + e * NMAT;  // vertex v at dout[v * T * NMAT]
         if constexpr (Q <= 11) {
             extern __shared__ double fl_lds[];
             const int bad = element_local_put<E, Q, NM, HA, 256>(
                 nid, x, g.tab, g.tabp, g.cm0, g.cm1, g.ca, fl_lds + threadIdx.x, [&](int p, int mat, double v) {
                     out[p * NMAT + mat] = v;
                     const int vd = vertex_of_diag_pair<E>(p);
-                    if (vd >= 0) dout[vd * T * NMAT + mat] = v;
+                    if (vd >= 0) dstage[(vd * T + e) * NMAT + mat] = v;
                 });
             if (bad) atomicAdd(g.degenerate, static_cast<unsigned long long>(bad));
         } else {
@@ -189,7 +188,7 @@ __device__ __forceinline__ void stage_body(const BlockArgs &g, int64_t T, const 
                     const double v = mat < NM ? LM[mat][p] : LA[p];
                     out[p * NMAT + mat] = v;
                     const int vd = vertex_of_diag_pair<E>(p);
-                    if (vd >= 0) dout[vd * T * NMAT + mat] = v;
+                    if (vd >= 0) dstage[(vd * T + e) * NMAT + mat] = v;
                 }
         }
     } else {
