@@ -386,3 +386,32 @@ def test_prebuilt_arguments(lf):
     lf.lfem_batch_destroy(b)
     for d in dms:
         d.close()
+
+
+def test_batch_member_schedule_built_later(lf):
+    """A P2-tetrahedron member (staged by default, no block schedule at
+    pattern build) whose block schedule is built after the batch was created,
+    by an explicit blocked request on its pattern: the batch notices the new
+    schedule generation, keeps the member on its staged launch, and its
+    replays still equal per-mesh assembly."""
+    ms = [meshgen.small_mesh("surface", 2, 2, size=3), meshgen.small_mesh("bulk", 3, 2, size=3)]
+    dms = [lf.DeviceMesh.from_dict(m) for m in ms]
+    for d in dms:
+        d.build_pattern()
+    assert lf.lfem_pattern_info(dms[1].pattern)["blocks"] == 0
+    w = lf.LFEM_M | lf.LFEM_A
+    b, vals = run_batch(lf, dms, w)
+    check_members(lf, ms, dms, vals, ("M", "A"), [(None, None)] * len(ms), "before")
+    blocked = dms[1].assemble(w, scatter=lf.LFEM_SCATTER_BLOCKED)  # builds the colour schedule
+    assert lf.lfem_pattern_info(dms[1].pattern)["blocks"] > 0
+    vals2 = [torch.full_like(v, float("nan")) for v in vals]
+    lf.lfem_assemble_batch(b, vals2)
+    torch.cuda.synchronize()
+    for v1, v2 in zip(vals, vals2):
+        assert torch.equal(v1, v2)
+    check_members(lf, ms, dms, vals2, ("M", "A"), [(None, None)] * len(ms), "after")
+    rp, ci = (x.cpu().numpy() for x in dms[1].pattern_tensors())
+    assert_csr_close(rp, ci, blocked["A"].cpu().numpy(), oracle.assemble(ms[1], "stiffness"), what="blocked A")
+    lf.lfem_batch_destroy(b)
+    for d in dms:
+        d.close()
