@@ -57,7 +57,7 @@ struct lfem_batch_s {
     bool captured = false;
     std::vector<double *> cap_vals;
     std::vector<const double *> cap_coords;
-    std::vector<const double *> cap_stage;
+    std::vector<const double *> cap_stage, cap_dstage;
 };
 
 namespace lfem {
@@ -302,22 +302,26 @@ void capture_graph(lfem_batch_s &b, double *const *vals, bool fast_only)
     b.cap_vals.assign(vals, vals + static_cast<size_t>(b.n) * b.nmat);
     b.cap_coords.resize(b.n);
     b.cap_stage.resize(b.n);
+    b.cap_dstage.resize(b.n);
     for (int i = 0; i < b.n; ++i) {
         b.cap_coords[i] = b.meshes[i]->coords;
         b.cap_stage[i] = b.pats[i]->stage;
+        b.cap_dstage[i] = b.pats[i]->dstage;
     }
 }
 
 // true when the graph must be captured again: none yet, or an output,
 // coordinate or staging-buffer pointer of a member outside the persistent
 // kernel differs from the captured one (another assembly on the same
-// pattern may have reallocated its staging buffer)
+// pattern may have reallocated its staging buffers)
 bool members_moved(const lfem_batch_s &b, double *const *vals)
 {
     if (!b.captured) return true;
     for (int i = 0; i < b.n; ++i) {
         if (b.fast[i]) continue;
-        if (b.meshes[i]->coords != b.cap_coords[i] || b.pats[i]->stage != b.cap_stage[i]) return true;
+        if (b.meshes[i]->coords != b.cap_coords[i] || b.pats[i]->stage != b.cap_stage[i] ||
+            b.pats[i]->dstage != b.cap_dstage[i])
+            return true;
         for (int j = 0; j < b.nmat; ++j) {
             const size_t k = static_cast<size_t>(i) * b.nmat + j;
             if (vals[k] != b.cap_vals[k]) return true;

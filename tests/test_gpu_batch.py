@@ -334,7 +334,7 @@ def test_batch_partial_coefficients(lf):
 
 def test_batch_member_state_changes(lf):
     """Changes the graph must follow: a member outside the persistent kernel
-    moved to new coordinates, and its pattern's staging buffer reallocated by
+    moved to new coordinates, and its pattern's staging buffers reallocated by
     a wider assembly on the same pattern between replays."""
     ms = mixed_family_meshes()
     dms = [lf.DeviceMesh.from_dict(m) for m in ms]
@@ -346,6 +346,11 @@ def test_batch_member_state_changes(lf):
     i = 4
     cc = torch.as_tensor(ms[i]["coef_c"], device="cuda")
     dms[i].assemble(lf.LFEM_M | lf.LFEM_A | lf.LFEM_MC, coef_c=cc)
+    # the P2 tetrahedra (staged by default): the same, which also regrows the
+    # array of vertex diagonals that their long-list reduction reads
+    k = 3
+    cc3 = torch.as_tensor(ms[k]["coef_c"], device="cuda")
+    dms[k].assemble(lf.LFEM_M | lf.LFEM_A | lf.LFEM_MC, coef_c=cc3)
     # the quartic planar mesh moved
     j = 5
     ms[j] = dict(ms[j], coords=ms[j]["coords"] * 1.25)
