@@ -226,7 +226,10 @@ lfem_status lfem_spmv(lfem_pattern_t p, const double *vals, const double *x, dou
  * N doubles, component-major, or NULL for the mesh's own coordinates.  The
  * linear solve is the caller's.  After one call (which builds the pattern's
  * lazy structures) a call allocates nothing, so it can be captured in a HIP
- * graph and replayed while the coordinates change in place.
+ * graph and replayed while the coordinates change in place.  A captured graph
+ * keeps the pattern's staging buffers: an assembly on the same pattern that
+ * needs larger ones (more matrices, staged) reallocates them, after which the
+ * graph must be captured again.
  * Errors: LFEM_EINVAL (handles, null buffers, non-finite tau), LFEM_EHIP.
  */
 lfem_status lfem_dziuk_system(lfem_mesh_t m, lfem_pattern_t p, double tau, const double *x,
