@@ -189,26 +189,57 @@ __global__ __launch_bounds__(NTR) void k_rows(int64_t N, int k, int64_t T,
     int len = 0;
     bool overflow = false;
     const double inv_t = 1.0 / static_cast<double>(T > 0 ? T : 1);
-    for (int32_t s = ne_ptr[i]; s < ne_ptr[i + 1] && !overflow; ++s) {
-        const int64_t e = inc_elem(ne[s], T, inv_t);
-        for (int b = 0; b < k; ++b) {
-            const int32_t j = conn[b * T + e];
-            int lo = 0, hi = len;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (buf[mid * NTR + t] < j)
-                    lo = mid + 1;
-                else
-                    hi = mid;
+    const int32_t s0 = ne_ptr[i], s1 = ne_ptr[i + 1];
+    if (RMAX > ROW_MAX && static_cast<int64_t>(s1 - s0) * k <= RMAX) {
+        // long rows of large elements, every candidate fitting: collect them
+        // with repeats, sort (Shell's method, Ciura's gaps: no quadratic cost
+        // when the incidences do not arrive in node order) and drop the
+        // repeats (for short rows the insertion below is faster)
+        int n = 0;
+        for (int32_t s = s0; s < s1; ++s) {
+            const int64_t e = inc_elem(ne[s], T, inv_t);
+            for (int b = 0; b < k; ++b) buf[(n++) * NTR + t] = conn[b * T + e];
+        }
+        constexpr int gaps[8] = {701, 301, 132, 57, 23, 10, 4, 1};
+        for (int gi = 0; gi < 8; ++gi) {
+            const int h = gaps[gi];
+            for (int r = h; r < n; ++r) {
+                const int32_t v = buf[r * NTR + t];
+                int q = r;
+                while (q >= h && buf[(q - h) * NTR + t] > v) {
+                    buf[q * NTR + t] = buf[(q - h) * NTR + t];
+                    q -= h;
+                }
+                buf[q * NTR + t] = v;
             }
-            if (lo < len && buf[lo * NTR + t] == j) continue;
-            if (len == RMAX) {
-                overflow = true;
-                break;
+        }
+        for (int r = 0; r < n; ++r) {
+            const int32_t v = buf[r * NTR + t];
+            if (len == 0 || buf[(len - 1) * NTR + t] != v) buf[(len++) * NTR + t] = v;
+        }
+    } else {
+        // insertion into the sorted row, which also detects a row longer than RMAX
+        for (int32_t s = s0; s < s1 && !overflow; ++s) {
+            const int64_t e = inc_elem(ne[s], T, inv_t);
+            for (int b = 0; b < k; ++b) {
+                const int32_t j = conn[b * T + e];
+                int lo = 0, hi = len;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (buf[mid * NTR + t] < j)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < len && buf[lo * NTR + t] == j) continue;
+                if (len == RMAX) {
+                    overflow = true;
+                    break;
+                }
+                for (int r = len; r > lo; --r) buf[r * NTR + t] = buf[(r - 1) * NTR + t];
+                buf[lo * NTR + t] = j;
+                ++len;
             }
-            for (int r = len; r > lo; --r) buf[r * NTR + t] = buf[(r - 1) * NTR + t];
-            buf[lo * NTR + t] = j;
-            ++len;
         }
     }
     if (overflow) atomicOr(&flags[2], 1);
